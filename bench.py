@@ -1,0 +1,200 @@
+"""Throughput benchmark: Generalized Euclidean node-vector distances per second.
+
+Workload (one GPU): Barabasi-Albert graph, n = 1,000,000, m = 3, unit
+weights; 64 vector pairs, each p and q uniform[0,1) on an independent random
+5% of the nodes; FP32 CG with FP64 iterative refinement to a true relative
+residual of 1e-8 (the headline path), and the plain FP64 CG solver to the
+same residual beside it.  One step = one nvd_distances call over all 64
+pairs (projection, CG, refinement, quadratic form), inputs resident in HBM.
+
+Prints one JSON line.  Also reported: the SpMM kernel's algorithmic bytes
+per launch over its event-timed duration (roofline), the oracle's CPU rate
+on a bounded sample, and the distances' largest relative error against the
+stored oracle values (tests/golden/c2_expected.json).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def load_golden():
+    p = os.path.join(ROOT, "tests", "golden", "c2_expected.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        g = json.load(f)
+    import numpy as np
+    return np.array([float(v) for v in g["d"]])
+
+
+def cpu_baseline(w, pairs):
+    """The oracle (FP64 Jacobi-PCG route, unmodified defaults) on `pairs`
+    pairs of the same workload, single-threaded."""
+    import numpy as np
+    import oracle
+    from threadpoolctl import threadpool_limits
+    g = w.graphs[0]
+    P = np.ascontiguousarray(w.P[0][:, :pairs])
+    Q = np.ascontiguousarray(w.Q[0][:, :pairs])
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        r = oracle.ge_pcg(g.n, g.row_ptr, g.col_idx, g.w, P, Q)
+        t1 = time.perf_counter()
+    return pairs / (t1 - t0), t1 - t0, r["d"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--cpu-pairs", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--inner-rtol", type=float, default=1e-5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU layout is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2310_11222_amd as nvd
+    from nvdgen import workload
+
+    torch.cuda.set_device(0)
+    log("generating workload")
+    t0 = time.perf_counter()
+    w = workload(2)
+    g = w.graphs[0]
+    log(f"n={g.n} nnz={g.nnz} gen {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    dg = nvd.Graph(g.row_ptr, g.col_idx, g.w)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    P = torch.as_tensor(w.P[0]).cuda()
+    Q = torch.as_tensor(w.Q[0]).cuda()
+    K = P.shape[1]
+    rtol = w.rtol
+    golden = load_golden()
+
+    def step(prec):
+        return dg.distances(P, Q, precision=prec, rtol=rtol, inner_rtol=args.inner_rtol,
+                            tile_k=args.tile)
+
+    # ---- mixed precision (headline)
+    for _ in range(args.warmup):
+        d, _, info = step("mixed")
+    torch.cuda.synchronize()
+    nvd.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        d, _, info = step("mixed")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = nvd.prof_read()
+    nvd.prof_enable(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = K * args.steps / (t1 - t0)
+    d_mixed = d.cpu().numpy()
+    iters_mixed = [i["iters"] for i in info]
+    refine = [i["refine_steps"] for i in info]
+    log(f"mixed: {ms_step:.2f} ms/step, {value:.1f} distances/s, iters {np.mean(iters_mixed):.1f}, refine {np.mean(refine):.2f}")
+
+    # ---- plain FP64 solver on the same GPU
+    d64, _, info64 = step("fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.fp64_steps):
+        d64, _, info64 = step("fp64")
+    torch.cuda.synchronize()
+    t64 = (time.perf_counter() - t0) / args.fp64_steps
+    value64 = K / t64
+    d64 = d64.cpu().numpy()
+    log(f"fp64: {t64 * 1e3:.2f} ms/step, {value64:.1f} distances/s")
+
+    # ---- accuracy vs stored oracle values
+    acc = {}
+    if golden is not None and golden.size == K:
+        acc["max_rel_err_mixed"] = float(np.max(np.abs(d_mixed - golden) / golden))
+        acc["max_rel_err_fp64"] = float(np.max(np.abs(d64 - golden) / golden))
+    else:
+        acc["max_rel_err_mixed"] = None
+        acc["max_rel_err_fp64"] = None
+    log(f"accuracy {acc}")
+
+    # ---- roofline of the dominant kernel (SpMM, FP32 in the inner solves)
+    def kern(name):
+        p = prof[name]
+        if p["launches"] == 0:
+            return None
+        avg_ms = p["ms"] / p["launches"]
+        bytes_per = p["bytes"] / p["launches"]
+        return {"avg_us": avg_ms * 1e3, "bytes_per_launch": bytes_per,
+                "gbs": bytes_per / (avg_ms * 1e-3) / 1e9, "launches": p["launches"],
+                "ms_total": p["ms"]}
+
+    kinds = {k: kern(k) for k in prof}
+    dom = max((k for k in kinds if kinds[k]), key=lambda k: kinds[k]["ms_total"])
+    sp = kinds["spmm_f32"]
+    roof = {"kernel": "k_spmm<float> (EPI_CG, Laplacian apply + p^T q)", "bound": "hbm",
+            "achieved": round(sp["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(sp["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": sp["bytes_per_launch"], "avg_launch_us": round(sp["avg_us"], 2)}
+    log(f"kernels: " + json.dumps({k: (round(v['gbs'], 1), round(v['ms_total'], 2)) for k, v in kinds.items() if v}))
+
+    # ---- CPU oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu and args.cpu_pairs > 0:
+        rate, secs, dref = cpu_baseline(w, args.cpu_pairs)
+        cpu = {"value": round(rate, 4), "unit": "distances/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {args.cpu_pairs} of the 64 pairs, FP64 Jacobi-PCG oracle route "
+                         f"(true rel. residual 1e-13), {secs:.1f} s single-threaded"}
+        log(f"cpu oracle {rate:.3f} distances/s ({secs:.1f}s)")
+
+    out = {
+        "metric": "NVD distances/sec at rel err <=1e-6 vs FP64 oracle; SpMV HBM GB/s % of peak",
+        "value": round(value, 2),
+        "unit": "distances/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "ba_n1e6_m3_unit_k64", "n": g.n, "nnz": g.nnz, "pairs": K,
+                   "rtol": rtol, "precision": "mixed (FP32 CG + FP64 refinement)",
+                   "inner_rtol": args.inner_rtol, "tile": args.tile or "auto"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp64_path": {"value": round(value64, 2), "unit": "distances/s",
+                      "ms_per_step": round(t64 * 1e3, 3)},
+        "accuracy": acc,
+        "iters_mean": float(np.mean(iters_mixed)),
+        "refine_mean": float(np.mean(refine)),
+        "setup_s": round(setup_s, 3),
+        "kernels": {k: v for k, v in kinds.items() if v},
+        "dominant_kernel": dom,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * nvd.h -- C ABI of the MI355X (gfx950) node-vector-distance library.
+ *
+ * The library computes the Generalized Euclidean (GE) distance between node
+ * vectors a, b on an undirected graph G with positive edge weights
+ * (Coscia & Devriendt, "Fast Node Vector Distance Computations using
+ * Laplacian Solvers", section 3.1):
+ *
+ *     d(a, b) = sqrt( (a - b)^T L^+ (a - b) ),   L = D - A,
+ *
+ * where A holds the edge weights, D the weighted degrees and L^+ is the
+ * Moore-Penrose pseudoinverse.  As in the paper's section 3.2, L^+ is never
+ * formed: L x = delta_bar is solved with a Laplacian solver (here
+ * Jacobi-preconditioned conjugate gradients on the GPU), where delta_bar is
+ * delta = a - b with its mean removed on every connected component, and
+ *
+ *     d^2 = delta_bar^T x + x^T r,   r = delta_bar - L x,
+ *
+ * evaluated in FP64 (equal to delta_bar^T x for an exact or Galerkin x; the
+ * x^T r term makes the error quadratic in the residual after refinement).
+ *
+ * Conventions (the paper fixes only the unit-weight case):
+ *   - weights are conductances: L_ii = sum_j w_ij, L_ij = -w_ij;
+ *   - self-loops are dropped on input (they cancel in D - A);
+ *   - an isolated node is its own component and contributes nothing;
+ *   - delta_bar = 0 gives d = 0 exactly, with no iterations.
+ *
+ * Layouts.  A graph is a symmetric CSR on the host: row_ptr int64 [n+1],
+ * col_idx int32 [nnz] (both directions of every edge present, equal weights,
+ * no repeated (i, j) within a row), weights float64 [nnz] or NULL for unit
+ * weights.  Node-vector blocks are row-major n x k float64 with a leading
+ * dimension ld >= k (element (i, j) at P[i*ld + j]), column j being pair j.
+ *
+ * Ownership.  A graph or batch handle owns device copies of everything it
+ * needs, plus its solver workspace (allocated on first use and cached); the
+ * caller's input arrays may be freed after the create call returns.  Buffers
+ * passed to solve calls stay owned by the caller.  A handle is not
+ * thread-safe: one call in flight per handle.
+ *
+ * Streams.  Every `stream` argument is a hipStream_t passed as void*
+ * (NULL = the default stream).  Solve calls enqueue their work on that stream
+ * and return after it has completed (they poll convergence flags on the
+ * host), so outputs are ready on return.
+ *
+ * Errors.  Every call returns an nvd_status.  Argument and graph errors are
+ * found before anything is enqueued; nvd_last_error() then holds a message
+ * (thread-local, valid until the next call on the same thread).  HIP failures
+ * return NVD_E_DEVICE.  Per-pair numerical outcomes (no convergence,
+ * breakdown) are reported in nvd_pair_info and, aggregated, in the return
+ * value as NVD_E_NOCONV / NVD_E_BREAKDOWN while every output is still
+ * written.  Nothing is printed and no call aborts the process.
+ */
+#ifndef NVD_H
+#define NVD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NVD_ABI_VERSION 1
+
+typedef enum nvd_status {
+  NVD_OK = 0,
+  NVD_E_ARG = 1,         /* bad argument (NULL pointer, k < 1, ld < k, ...) */
+  NVD_E_GRAPH = 2,       /* invalid CSR: not monotone, column out of range,
+                            asymmetric, repeated entry, bad weight */
+  NVD_E_VALUE = 3,       /* non-finite value in a node vector */
+  NVD_E_NOCONV = 4,      /* at least one pair hit max_iter / max_refine */
+  NVD_E_BREAKDOWN = 5,   /* at least one pair lost positivity (p^T L p <= 0) */
+  NVD_E_DEVICE = 6,      /* a HIP call failed */
+  NVD_E_NOMEM = 7,       /* device allocation failed */
+  NVD_E_UNSUPPORTED = 8  /* valid request beyond this build's limits */
+} nvd_status;
+
+/* nvd_opts.precision */
+enum { NVD_FP64 = 0, NVD_MIXED = 1 };
+/* dtype of nvd_laplacian_apply */
+enum { NVD_DT_F64 = 0, NVD_DT_F32 = 1 };
+/* nvd_opts.flags */
+enum {
+  NVD_WARM_START = 1u  /* X_inout holds a starting guess on entry */
+};
+
+typedef struct nvd_graph nvd_graph;
+typedef struct nvd_batch nvd_batch;
+
+typedef struct nvd_opts {
+  int32_t precision;   /* NVD_FP64: all CG arithmetic in FP64.  NVD_MIXED:
+                          inner CG in FP32, outer residual delta_bar - L x,
+                          its norm and the update of x in FP64 (iterative
+                          refinement). */
+  double rtol;         /* stop when ||delta_bar - L x|| <= rtol ||delta_bar||
+                          (relative 2-norm per pair; default 1e-10) */
+  double inner_rtol;   /* MIXED: relative residual of each inner FP32 solve
+                          (default 1e-5) */
+  int32_t max_iter;    /* CG iterations per pair (FP64) or per inner solve
+                          (MIXED); default 20000 */
+  int32_t max_refine;  /* MIXED: outer refinement steps; default 30 */
+  int32_t tile_k;      /* columns per SpMM pass: 1,2,4,8,16,32,64; 0 = the
+                          library's autotuned choice */
+  uint32_t flags;      /* NVD_WARM_START */
+} nvd_opts;
+
+typedef struct nvd_pair_info {
+  int32_t status;       /* NVD_OK, NVD_E_NOCONV or NVD_E_BREAKDOWN */
+  int32_t iters;        /* CG iterations (all inner solves summed) */
+  int32_t refine_steps; /* MIXED outer steps (0 for FP64) */
+  int32_t reserved;
+  double rel_res;       /* final true ||delta_bar - L x|| / ||delta_bar|| */
+  double dsq_plain;     /* delta_bar^T x */
+  double dsq;           /* delta_bar^T x + x^T r (returned d = sqrt(max(dsq,0))) */
+} nvd_pair_info;
+
+typedef struct nvd_stats {
+  int64_t n;            /* nodes */
+  int64_t nnz;          /* stored off-diagonal entries (2 |E|) */
+  int64_t n_comp;       /* connected components (isolated nodes included) */
+  int64_t n_isolated;   /* nodes of degree 0 */
+  int64_t max_deg;      /* largest number of neighbours */
+  int64_t n_long_rows;  /* rows handled by the split-row path of the SpMM */
+  int64_t device_bytes; /* device memory held by the handle (workspace incl.) */
+  int32_t weighted;     /* 1 if explicit weights were given */
+  int32_t self_loops_dropped; /* number of diagonal entries removed on input */
+} nvd_stats;
+
+/* ---- library ----------------------------------------------------------- */
+int32_t nvd_abi_version(void);
+const char* nvd_status_string(int32_t status);
+/* Message of the last failing call on this thread ("" if none). */
+const char* nvd_last_error(void);
+/* Fills *o with the defaults listed in nvd_opts. */
+nvd_status nvd_opts_default(nvd_opts* o);
+
+/* ---- graph (operator setup; the paper excludes this preprocessing from its
+ *      timings, section 5.2) ------------------------------------------------
+ * Validates the host CSR (see Layouts), drops self-loops, uploads it,
+ * computes weighted degrees and their inverses (0 for isolated nodes),
+ * FP32 copies, connected-component labels (for the per-component mean
+ * removal) and the list of long rows for the SpMM's split-row path.
+ * Limits: n < 2^31, nnz < 2^31 (NVD_E_UNSUPPORTED otherwise). */
+nvd_status nvd_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col_idx, const double* weights,
+                            void* stream, nvd_graph** out);
+nvd_status nvd_graph_destroy(nvd_graph* g);
+nvd_status nvd_graph_stats(const nvd_graph* g, nvd_stats* s);
+/* Host copies of the component label of every node (int32 [n], labels
+ * 0..n_comp-1 numbered by each component's smallest node) and of the
+ * weighted degree (float64 [n]).  Either pointer may be NULL. */
+nvd_status nvd_graph_query(const nvd_graph* g, int32_t* labels_host,
+                           double* degree_host);
+
+/* ---- Laplacian apply: Y = L X (section 3.1's L = D - A) ----------------
+ * X, Y: device, row-major n x k with leading dimensions ldx, ldy, element
+ * type float64 (dtype NVD_DT_F64, FP64 weights) or float32 (NVD_DT_F32, the
+ * graph's FP32 weight copy).  X and Y must not overlap.  Asynchronous:
+ * returns once enqueued. */
+nvd_status nvd_laplacian_apply(nvd_graph* g, int32_t dtype, int32_t k,
+                               const void* X, int64_t ldx, void* Y,
+                               int64_t ldy, void* stream);
+
+/* ---- projection: delta_bar = (P - Q) minus its mean on every component --
+ * P, Q: device float64 n x k (ld); Dbar: device float64 n x k (ldd);
+ * norms: device float64 [k] receives ||delta_bar_j||_2 (may be NULL).
+ * Asynchronous. */
+nvd_status nvd_project(nvd_graph* g, int32_t k, const double* P,
+                       const double* Q, int64_t ld, double* Dbar, int64_t ldd,
+                       double* norms, void* stream);
+
+/* ---- distances (the paper's GE computation, section 3.1 via 3.2) ---------
+ * P, Q: device float64 n x k (ld) -- pair j is (P[:, j], Q[:, j]).
+ * opts: NULL for defaults.
+ * d_out: device float64 [k] receives d_j.
+ * X_inout: device float64 n x k (ldx) or NULL; on return holds x_j = L^+
+ *   delta_j (mean zero on every component).  With NVD_WARM_START it also
+ *   supplies the starting guess.
+ * info: host array of k nvd_pair_info or NULL.
+ * Synchronous with respect to `stream` (see Streams). */
+nvd_status nvd_distances(nvd_graph* g, int32_t k, const double* P,
+                         const double* Q, int64_t ld, const nvd_opts* opts,
+                         double* d_out, double* X_inout, int64_t ldx,
+                         nvd_pair_info* info, void* stream);
+
+/* ---- adjoint of d^2 with respect to the edge weights ---------------------
+ * Given X (device float64 n x k, ldx; normally the X_inout of a previous
+ * nvd_distances call) and gscale (device float64 [k], the upstream
+ * dLoss/d(d_j^2)), writes for every entry e = (i, j) of the CSR passed to
+ * nvd_graph_create (same order, self-loop entries get 0):
+ *     grad_w[e] = -1/2 * sum_j gscale_j * (X[i, j] - X[c, j])^2,  c = col_idx[e],
+ * so that the two stored directions of an edge sum to d(sum_j g_j d_j^2)/dw
+ * of that undirected edge.  The gradients with respect to P and Q are
+ * 2 X diag(gscale) and its negative (no kernel needed).  grad_w: device
+ * float64 [nnz].  Asynchronous. */
+nvd_status nvd_grad_weights(nvd_graph* g, int32_t k, const double* X,
+                            int64_t ldx, const double* gscale, double* grad_w,
+                            void* stream);
+
+/* ---- batches of graphs ----------------------------------------------------
+ * nvd_batch_create packs G graphs into one device structure (the graphs may
+ * be destroyed afterwards).  nvd_batch_distances solves k_g pairs on every
+ * graph g in one persistent launch: FP32 CG with FP64 iterative refinement
+ * (opts->precision NVD_MIXED, the default for batches) or FP64 CG.
+ * k_per_graph: host int32 [G] (each 1..64).
+ * P, Q: device float64, graph-major packed: graph g's block is n_g x k_g
+ *   row-major (leading dimension k_g) starting at element offset
+ *   sum_{h<g} n_h k_h.
+ * d_out: device float64 [sum k_g] (graph-major).  X_out: NULL or device
+ *   float64 packed like P.  info: NULL or host [sum k_g].
+ * Synchronous with respect to `stream`. */
+nvd_status nvd_batch_create(int32_t G, nvd_graph* const* graphs, void* stream,
+                            nvd_batch** out);
+nvd_status nvd_batch_destroy(nvd_batch* b);
+nvd_status nvd_batch_distances(nvd_batch* b, const int32_t* k_per_graph,
+                               const double* P, const double* Q,
+                               const nvd_opts* opts, double* d_out,
+                               double* X_out, nvd_pair_info* info,
+                               void* stream);
+
+/* ---- launch timing (instrumentation) -------------------------------------
+ * When enabled, every launch of the solver's SpMM, CG-update and
+ * CG-direction kernels is bracketed by HIP events on its stream.
+ * nvd_prof_read (host arrays of NVD_PROF_KINDS entries) returns, per kind,
+ * the summed kernel milliseconds, the launch count and the algorithmic
+ * bytes those launches must move (CSR once, each vector stream once), then
+ * clears the record.  Kinds: 0 SpMM FP64, 1 SpMM FP32, 2 update FP64,
+ * 3 update FP32, 4 direction FP64, 5 direction FP32, 6 other. */
+#define NVD_PROF_KINDS 7
+nvd_status nvd_prof_enable(int32_t on);
+nvd_status nvd_prof_read(double* ms, int64_t* launches, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NVD_H */

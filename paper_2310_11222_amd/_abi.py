@@ -1,0 +1,100 @@
+"""ctypes declarations of the C ABI in include/nvd.h (argument marshalling
+only; every numerical step runs inside libnvd.so)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnvd.so")
+
+NVD_OK, NVD_E_ARG, NVD_E_GRAPH, NVD_E_VALUE, NVD_E_NOCONV, NVD_E_BREAKDOWN, \
+    NVD_E_DEVICE, NVD_E_NOMEM, NVD_E_UNSUPPORTED = range(9)
+NVD_FP64, NVD_MIXED = 0, 1
+NVD_DT_F64, NVD_DT_F32 = 0, 1
+NVD_WARM_START = 1
+
+
+class NvdOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("rtol", C.c_double), ("inner_rtol", C.c_double),
+                ("max_iter", C.c_int32), ("max_refine", C.c_int32), ("tile_k", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class PairInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("refine_steps", C.c_int32),
+                ("reserved", C.c_int32), ("rel_res", C.c_double), ("dsq_plain", C.c_double),
+                ("dsq", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("n_comp", C.c_int64),
+                ("n_isolated", C.c_int64), ("max_deg", C.c_int64), ("n_long_rows", C.c_int64),
+                ("device_bytes", C.c_int64), ("weighted", C.c_int32),
+                ("self_loops_dropped", C.c_int32)]
+
+
+_P = C.c_void_p
+_I32 = C.c_int32
+_I64 = C.c_int64
+_D = C.c_double
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "nvd_abi_version": (_I32, []),
+    "nvd_status_string": (C.c_char_p, [_I32]),
+    "nvd_last_error": (C.c_char_p, []),
+    "nvd_opts_default": (_I32, [C.POINTER(NvdOpts)]),
+    "nvd_graph_create": (_I32, [_I64, _I64, _P, _P, _P, _P, C.POINTER(_P)]),
+    "nvd_graph_destroy": (_I32, [_P]),
+    "nvd_graph_stats": (_I32, [_P, C.POINTER(Stats)]),
+    "nvd_graph_query": (_I32, [_P, _P, _P]),
+    "nvd_laplacian_apply": (_I32, [_P, _I32, _I32, _P, _I64, _P, _I64, _P]),
+    "nvd_project": (_I32, [_P, _I32, _P, _P, _I64, _P, _I64, _P, _P]),
+    "nvd_distances": (_I32, [_P, _I32, _P, _P, _I64, C.POINTER(NvdOpts), _P, _P, _I64,
+                             _P, _P]),
+    "nvd_grad_weights": (_I32, [_P, _I32, _P, _I64, _P, _P, _P]),
+    "nvd_batch_create": (_I32, [_I32, _P, _P, C.POINTER(_P)]),
+    "nvd_batch_destroy": (_I32, [_P]),
+    "nvd_batch_distances": (_I32, [_P, _P, _P, _P, C.POINTER(NvdOpts), _P, _P, _P, _P]),
+    "nvd_prof_enable": (_I32, [_I32]),
+    "nvd_prof_read": (_I32, [_P, _P, _P]),
+}
+
+NVD_PROF_KINDS = 7
+PROF_KIND_NAMES = ["spmm_f64", "spmm_f32", "update_f64", "update_f32", "direction_f64",
+                   "direction_f32", "other"]
+
+_lib = None
+
+
+class NvdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Load libnvd.so and declare every entry point.  Raises loudly if the
+    library has not been built: there is no fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"libnvd.so not found at {path}; build it first with "
+            "`python -m paper_2310_11222_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status, what=""):
+    if status != NVD_OK:
+        lib = load()
+        msg = lib.nvd_last_error().decode() or lib.nvd_status_string(status).decode()
+        raise NvdError(status, f"{what}: {msg}" if what else msg)

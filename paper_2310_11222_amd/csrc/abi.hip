@@ -1,0 +1,306 @@
+// The extern "C" entry points declared in include/nvd.h: argument checks,
+// tiling of the k pairs, and the edge-weight adjoint kernel.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "device_common.hpp"
+
+namespace nvd {
+
+nvd_status graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                        const double* w, hipStream_t s, DevGraph** out);
+nvd_status graph_destroy(DevGraph* g);
+
+// Edge-weight adjoint: one thread per (row, column) pair of a tile is too
+// fine for short rows, so a group of T lanes takes one row and walks its
+// neighbours; each CSR entry's value is the sum over the tile's columns,
+// reduced across the T lanes by shuffles.
+template <int T>
+__global__ __launch_bounds__(kBS) void k_grad_w(int n, const int* rp, const int* ci,
+                                                const int* in_pos, const double* X, long ldx,
+                                                const double* gs, double* gw, int accumulate) {
+  constexpr int RW = 64 / T;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int c = lane % T;
+  const int g = lane / T;
+  const double gc = gs[c];
+  const long rows_per_step = (long)gridDim.x * (kBS / 64) * RW;
+  for (long row = (long)blockIdx.x * (kBS / 64) * RW + (t >> 6) * RW + g; row < n;
+       row += rows_per_step) {
+    const double xi = X[row * ldx + c];
+    const int lo = rp[row], hi = rp[row + 1];
+    for (int e = lo; e < hi; ++e) {
+      const double df = xi - X[(long)ci[e] * ldx + c];
+      double v = -0.5 * gc * df * df;
+#pragma unroll
+      for (int off = 1; off < T; off <<= 1) v += __shfl_xor(v, off, 64);
+      if (c == 0) {
+        const long pos = in_pos ? in_pos[e] : e;
+        gw[pos] = accumulate ? gw[pos] + v : v;
+      }
+    }
+  }
+}
+
+}  // namespace nvd
+
+using namespace nvd;
+
+struct nvd_graph {
+  DevGraph* g;
+};
+
+struct nvd_batch;   // defined in batch.hip
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" {
+
+int32_t nvd_abi_version(void) { return NVD_ABI_VERSION; }
+
+const char* nvd_status_string(int32_t s) {
+  switch (s) {
+    case NVD_OK: return "ok";
+    case NVD_E_ARG: return "invalid argument";
+    case NVD_E_GRAPH: return "invalid graph";
+    case NVD_E_VALUE: return "non-finite value in input";
+    case NVD_E_NOCONV: return "did not converge";
+    case NVD_E_BREAKDOWN: return "solver breakdown";
+    case NVD_E_DEVICE: return "device error";
+    case NVD_E_NOMEM: return "out of device memory";
+    case NVD_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* nvd_last_error(void) { return get_error(); }
+
+nvd_status nvd_opts_default(nvd_opts* o) {
+  if (!o) {
+    set_error("nvd_opts_default: NULL");
+    return NVD_E_ARG;
+  }
+  o->precision = NVD_FP64;
+  o->rtol = 1e-10;
+  o->inner_rtol = 1e-5;
+  o->max_iter = 20000;
+  o->max_refine = 30;
+  o->tile_k = 0;
+  o->flags = 0;
+  return NVD_OK;
+}
+
+nvd_status nvd_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col_idx, const double* weights, void* stream,
+                            nvd_graph** out) {
+  set_error("");
+  if (!out) {
+    set_error("nvd_graph_create: out is NULL");
+    return NVD_E_ARG;
+  }
+  *out = nullptr;
+  DevGraph* g = nullptr;
+  NVD_TRY(graph_create(n, nnz, row_ptr, col_idx, weights, as_stream(stream), &g));
+  *out = new nvd_graph{g};
+  return NVD_OK;
+}
+
+nvd_status nvd_graph_destroy(nvd_graph* g) {
+  if (!g) return NVD_OK;
+  graph_destroy(g->g);
+  delete g;
+  return NVD_OK;
+}
+
+nvd_status nvd_graph_stats(const nvd_graph* h, nvd_stats* s) {
+  if (!h || !s) {
+    set_error("nvd_graph_stats: NULL argument");
+    return NVD_E_ARG;
+  }
+  const DevGraph* g = h->g;
+  s->n = g->n;
+  s->nnz = g->nnz;
+  s->n_comp = g->n_comp;
+  s->n_isolated = g->n_isolated;
+  s->max_deg = g->max_deg;
+  s->n_long_rows = g->n_long_rows;
+  s->device_bytes = g->bytes;
+  s->weighted = g->weighted ? 1 : 0;
+  s->self_loops_dropped = g->self_loops;
+  return NVD_OK;
+}
+
+nvd_status nvd_graph_query(const nvd_graph* h, int32_t* labels, double* degree) {
+  if (!h) {
+    set_error("nvd_graph_query: NULL graph");
+    return NVD_E_ARG;
+  }
+  const DevGraph* g = h->g;
+  if (labels) std::copy(g->h_comp.begin(), g->h_comp.end(), labels);
+  if (degree) NVD_HIP(hipMemcpy(degree, g->deg64, sizeof(double) * g->n, hipMemcpyDeviceToHost));
+  return NVD_OK;
+}
+
+nvd_status nvd_laplacian_apply(nvd_graph* h, int32_t dtype, int32_t k, const void* X,
+                               int64_t ldx, void* Y, int64_t ldy, void* stream) {
+  set_error("");
+  if (!h || !X || !Y || k < 1 || ldx < k || ldy < k) {
+    set_error("nvd_laplacian_apply: bad argument (NULL pointer, k < 1 or ld < k)");
+    return NVD_E_ARG;
+  }
+  if (dtype != NVD_DT_F64 && dtype != NVD_DT_F32) {
+    set_error("nvd_laplacian_apply: dtype must be NVD_DT_F64 or NVD_DT_F32");
+    return NVD_E_ARG;
+  }
+  DevGraph* g = h->g;
+  NVD_TRY(ensure_workspace(g, 1, false));
+  const size_t es = dtype == NVD_DT_F64 ? 8 : 4;
+  for (int c0 = 0; c0 < k;) {
+    int T = 64;
+    while (T > k - c0) T >>= 1;
+    SpmmCall sc{};
+    sc.g = g;
+    sc.prec = dtype == NVD_DT_F64 ? 0 : 1;
+    sc.T = T;
+    sc.x = static_cast<const char*>(X) + c0 * es;
+    sc.ldx = ldx;
+    sc.y = static_cast<char*>(Y) + c0 * es;
+    sc.ldy = ldy;
+    sc.epi = EPI_PLAIN;
+    NVD_TRY(launch_spmm(sc, g->ws->red, as_stream(stream)));
+    c0 += T;
+  }
+  return NVD_OK;
+}
+
+nvd_status nvd_project(nvd_graph* h, int32_t k, const double* P, const double* Q, int64_t ld,
+                       double* Dbar, int64_t ldd, double* norms, void* stream) {
+  set_error("");
+  if (!h || !P || !Q || !Dbar || k < 1 || ld < k || ldd < k) {
+    set_error("nvd_project: bad argument (NULL pointer, k < 1 or ld < k)");
+    return NVD_E_ARG;
+  }
+  for (int c0 = 0; c0 < k;) {
+    int T = 64;
+    while (T > k - c0) T >>= 1;
+    NVD_TRY(project_tile(h->g, T, P + c0, Q + c0, ld, Dbar + c0, ldd, norms ? norms + c0 : nullptr,
+                         as_stream(stream)));
+    c0 += T;
+  }
+  return NVD_OK;
+}
+
+static nvd_status check_opts(const nvd_opts* o) {
+  if (o->precision != NVD_FP64 && o->precision != NVD_MIXED) {
+    set_error("nvd_opts.precision must be NVD_FP64 or NVD_MIXED");
+    return NVD_E_ARG;
+  }
+  if (!(o->rtol > 0.0) || !(o->rtol < 1.0) || !(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0)) {
+    set_error("nvd_opts: rtol and inner_rtol must lie in (0, 1)");
+    return NVD_E_ARG;
+  }
+  if (o->max_iter < 1 || o->max_refine < 1) {
+    set_error("nvd_opts: max_iter and max_refine must be >= 1");
+    return NVD_E_ARG;
+  }
+  const int t = o->tile_k;
+  if (t != 0 && t != 1 && t != 2 && t != 4 && t != 8 && t != 16 && t != 32 && t != 64) {
+    set_error("nvd_opts.tile_k must be 0 or a power of two up to 64");
+    return NVD_E_ARG;
+  }
+  return NVD_OK;
+}
+
+nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double* Q, int64_t ld,
+                         const nvd_opts* opts, double* d_out, double* X, int64_t ldx,
+                         nvd_pair_info* info, void* stream) {
+  set_error("");
+  if (!h || !P || !Q || !d_out || k < 1 || ld < k || (X && ldx < k)) {
+    set_error("nvd_distances: bad argument (NULL pointer, k < 1 or ld < k)");
+    return NVD_E_ARG;
+  }
+  nvd_opts o;
+  nvd_opts_default(&o);
+  if (opts) o = *opts;
+  NVD_TRY(check_opts(&o));
+  if ((o.flags & NVD_WARM_START) && !X) {
+    set_error("nvd_distances: NVD_WARM_START needs X_inout");
+    return NVD_E_ARG;
+  }
+  DevGraph* g = h->g;
+  hipStream_t s = as_stream(stream);
+  SolveParams sp{};
+  sp.precision = o.precision;
+  sp.rtol = o.rtol;
+  sp.inner_rtol = o.inner_rtol;
+  sp.max_iter = o.max_iter;
+  sp.max_refine = o.max_refine;
+  sp.warm = (o.flags & NVD_WARM_START) != 0;
+  int tile = o.tile_k;
+  if (tile == 0) tile = choose_tile(g, k, o.precision, s);
+  // device buffer for the per-pair info of one tile
+  nvd_pair_info* info_dev = nullptr;
+  NVD_HIP(hipMalloc((void**)&info_dev, sizeof(nvd_pair_info) * kMaxTile));
+  std::vector<nvd_pair_info> hinfo(k);
+  nvd_status agg = NVD_OK;
+  nvd_status st = NVD_OK;
+  for (int c0 = 0; c0 < k && st == NVD_OK;) {
+    int T = tile;
+    while (T > k - c0) T >>= 1;
+    st = solve_tile(g, T, P + c0, Q + c0, ld, sp, d_out + c0, X ? X + c0 : nullptr, ldx,
+                    info_dev, s);
+    if (st == NVD_OK) {
+      hipError_t e = hipMemcpyAsync(hinfo.data() + c0, info_dev, sizeof(nvd_pair_info) * T,
+                                    hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) {
+        set_error(std::string("nvd_distances: ") + hipGetErrorString(e));
+        st = NVD_E_DEVICE;
+      }
+    }
+    c0 += T;
+  }
+  (void)hipFree(info_dev);
+  if (st != NVD_OK) return st;
+  for (int j = 0; j < k; ++j) {
+    if (hinfo[j].status == NVD_E_BREAKDOWN) agg = NVD_E_BREAKDOWN;
+    else if (hinfo[j].status == NVD_E_NOCONV && agg == NVD_OK) agg = NVD_E_NOCONV;
+  }
+  if (info) std::copy(hinfo.begin(), hinfo.end(), info);
+  if (agg != NVD_OK) set_error("nvd_distances: some pairs did not converge (see info)");
+  return agg;
+}
+
+nvd_status nvd_grad_weights(nvd_graph* h, int32_t k, const double* X, int64_t ldx,
+                            const double* gscale, double* grad_w, void* stream) {
+  set_error("");
+  if (!h || !X || !gscale || !grad_w || k < 1 || ldx < k) {
+    set_error("nvd_grad_weights: bad argument");
+    return NVD_E_ARG;
+  }
+  DevGraph* g = h->g;
+  hipStream_t s = as_stream(stream);
+  if (g->in_pos) NVD_HIP(hipMemsetAsync(grad_w, 0, sizeof(double) * g->nnz_in, s));
+  for (int c0 = 0; c0 < k;) {
+    int T = 64;
+    while (T > k - c0) T >>= 1;
+    const int rows_per_block = (kBS / 64) * (64 / T);
+    long grid = (g->n + rows_per_block - 1) / rows_per_block;
+    grid = std::min<long>(std::max<long>(grid, 1), 8192);
+    const int acc = c0 > 0 ? 1 : 0;
+    switch (T) {
+#define NVD_G(TT) \
+  case TT: k_grad_w<TT><<<grid, kBS, 0, s>>>(g->n, g->rp, g->ci, g->in_pos, X + c0, ldx, gscale + c0, grad_w, acc); break;
+      NVD_G(1) NVD_G(2) NVD_G(4) NVD_G(8) NVD_G(16) NVD_G(32) NVD_G(64)
+#undef NVD_G
+      default: break;
+    }
+    NVD_HIP(hipGetLastError());
+    c0 += T;
+  }
+  return NVD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,691 @@
+// Jacobi-preconditioned conjugate gradients for L x = delta_bar on one graph,
+// a tile of T independent right-hand sides at a time (the paper's section 3.2
+// replaces L^+ by such a Laplacian solve), and the FP64 quadratic form.
+//
+// Per CG iteration (per column c, preconditioner M = D):
+//   q = L p                 sigma = p^T q        alpha = rho / sigma   (SpMM, EPI_CG)
+//   x += alpha p; r -= alpha q; z = r / deg;  rho' = r^T z; ||r||^2   (k_update)
+//   beta = rho' / rho; p = z + beta p                                  (k_direction)
+// Every reduction finishes on the device (last block of the grid), so the
+// host only polls one word per chunk of iterations.
+//
+// Precision modes:
+//   FP64  : all of the above in FP64; at the end x is made mean-zero per
+//           component and the true residual r = delta_bar - L x is taken in
+//           FP64 (restarting CG from it if it is above rtol).
+//   MIXED : outer iterative refinement in FP64 -- r = delta_bar - L x (FP64
+//           operator), per-component mean removal, ||r|| -- around an inner
+//           FP32 CG solve of L c = r to inner_rtol; x += c in FP64.
+// Both return d^2 = delta_bar^T x + x^T r from the final FP64 residual.
+#include <algorithm>
+#include <cmath>
+
+#include "device_common.hpp"
+#include "prof.hpp"
+
+namespace nvd {
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+struct ProjSrc {
+  const double* a;   // first operand (row-major, lda)
+  long lda;
+  const double* b;   // optional second operand subtracted (ldb), may be null
+  long ldb;
+};
+
+// Column sums of (a - b) over all rows; the grid's last block stores
+// mean[c] = sum / n (single-component graphs).
+template <int T>
+__global__ __launch_bounds__(kBS) void k_colsum(int n, ProjSrc src, ColState* cs, GridRed red) {
+  __shared__ double sh[kBS];
+  __shared__ double vals[kMaxTile];
+  const int t = threadIdx.x;
+  const int c = t % T;
+  constexpr int RPB = kBS / T;
+  double acc[1][1] = {{0.0}};
+  for (long i = (long)blockIdx.x * RPB + t / T; i < n; i += (long)gridDim.x * RPB) {
+    double v = src.a[i * src.lda + c];
+    if (src.b) v -= src.b[i * src.ldb + c];
+    acc[0][0] += v;
+  }
+  block_reduce_cols<kBS, 1, 1>(acc, T, sh);
+  if (t < T) vals[t] = sh[t];
+  __syncthreads();
+  if (!grid_reduce<kBS>(vals, T, red)) return;
+  if (t < T) cs->mean[t] = vals[t] / (double)n;
+}
+
+// Per-component means of (a - b): one block per component.
+template <int T>
+__global__ __launch_bounds__(kBS) void k_comp_mean(int ncomp, const int* perm, const int* off,
+                                                   ProjSrc src, double* cmean) {
+  __shared__ double sh[kBS];
+  const int t = threadIdx.x;
+  const int c = t % T;
+  constexpr int RPB = kBS / T;
+  for (int k = blockIdx.x; k < ncomp; k += gridDim.x) {
+    const int lo = off[k], hi = off[k + 1];
+    double acc[1][1] = {{0.0}};
+    for (int p = lo + t / T; p < hi; p += RPB) {
+      const long i = perm[p];
+      double v = src.a[i * src.lda + c];
+      if (src.b) v -= src.b[i * src.ldb + c];
+      acc[0][0] += v;
+    }
+    block_reduce_cols<kBS, 1, 1>(acc, T, sh);
+    if (t < T) cmean[(long)k * kMaxTile + t] = sh[t] / (double)(hi - lo);
+    __syncthreads();
+  }
+}
+
+// Where a projection takes its means from.
+struct MeanSrc {
+  const double* colmean;   // [T] (single component) or null
+  const double* cmean;     // [ncomp][kMaxTile] or null
+  const int* comp;
+  const double* dots_sum;  // mean = dots_sum[c] / n (sum from a residual pass) or null
+  int n;
+};
+
+__device__ __forceinline__ double mean_of(const MeanSrc& m, long i, int c) {
+  if (m.cmean) return m.cmean[(long)m.comp[i] * kMaxTile + c];
+  if (m.colmean) return m.colmean[c];
+  if (m.dots_sum) return m.dots_sum[c] / (double)m.n;
+  return 0.0;
+}
+
+// delta_bar = (P - Q) - mean; b = delta_bar; x = 0; for the FP64 solver also
+// r = delta_bar, p = D^-1 r, q = 0 and rho = r^T D^-1 r.  Padding beyond n*T
+// is zeroed.
+template <int T>
+__global__ __launch_bounds__(kBS) void k_proj_init(int n, long cap, ProjSrc src, MeanSrc m,
+                                                   const double* invd, double* b64, double* x64,
+                                                   double* r64, double* p64, double* q64,
+                                                   int fp64cg, ColState* cs, GridRed red) {
+  __shared__ double sh[2 * kBS];
+  __shared__ double vals[2 * kMaxTile];
+  const int t = threadIdx.x;
+  double acc[2][1] = {{0.0}, {0.0}};
+  for (long e = (long)blockIdx.x * kBS + t; e < cap; e += (long)gridDim.x * kBS) {
+    const long i = e / T;
+    const int c = (int)(e % T);
+    double v = 0.0;
+    if (i < n) {
+      v = src.a[i * src.lda + c] - src.b[i * src.ldb + c] - mean_of(m, i, c);
+      acc[0][0] += v * v;
+      acc[1][0] += v * v * invd[i];
+    }
+    b64[e] = v;
+    x64[e] = 0.0;
+    if (fp64cg) {
+      r64[e] = v;
+      p64[e] = i < n ? v * invd[i] : 0.0;   // p0 = z0 = D^-1 r0
+      q64[e] = 0.0;
+    }
+  }
+  block_reduce_cols<kBS, 2, 1>(acc, T, sh);
+  if (t < T) {
+    vals[t] = sh[t];
+    vals[T + t] = sh[kBS + t];
+  }
+  __syncthreads();
+  if (!grid_reduce<kBS>(vals, 2 * T, red)) return;
+  if (t < T) {
+    const double bb = vals[t];
+    cs->obnorm2[t] = bb;
+    cs->bnorm2[t] = bb;
+    cs->orr[t] = bb;
+    cs->rho[t] = vals[T + t];
+    cs->alpha[t] = 0.0;
+    cs->beta[t] = 0.0;
+    const int act = bb > 0.0;
+    cs->oactive[t] = act;
+    cs->active[t] = fp64cg ? act : 0;
+    cs->iters[t] = 0;
+    cs->it_cur[t] = 0;
+    cs->refine[t] = 0;
+    cs->status[t] = kStOk;
+  }
+  recount_active(cs, T);
+}
+
+// x += alpha p; r -= alpha q; rho' = r^T D^-1 r; ||r||^2.  The grid's last
+// block forms beta and retires converged columns.
+template <typename V, int T>
+__global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__ x,
+                                                V* __restrict__ r, const V* __restrict__ p,
+                                                const V* __restrict__ q,
+                                                const V* __restrict__ invd, double rtol2,
+                                                int max_iter, ColState* cs, GridRed red) {
+  using VT = typename Vec16<V>::type;
+  constexpr int N = Vec16<V>::N;
+  __shared__ double sh[2 * kBS * N];
+  __shared__ double vals[2 * kMaxTile];
+  if (cs->n_active == 0) return;
+  const int t = threadIdx.x;
+  V al[N];
+#pragma unroll
+  for (int v = 0; v < N; ++v) al[v] = (V)cs->alpha[(t * N + v) % T];
+  double acc[2][N];
+#pragma unroll
+  for (int v = 0; v < N; ++v) acc[0][v] = acc[1][v] = 0.0;
+  const long nv = cap / N;
+  for (long i = (long)blockIdx.x * kBS + t; i < nv; i += (long)gridDim.x * kBS) {
+    VT xv = reinterpret_cast<const VT*>(x)[i];
+    VT rv = reinterpret_cast<const VT*>(r)[i];
+    const VT pv = reinterpret_cast<const VT*>(p)[i];
+    const VT qv = reinterpret_cast<const VT*>(q)[i];
+    V* xs = reinterpret_cast<V*>(&xv);
+    V* rs = reinterpret_cast<V*>(&rv);
+    const V* ps = reinterpret_cast<const V*>(&pv);
+    const V* qs = reinterpret_cast<const V*>(&qv);
+#pragma unroll
+    for (int v = 0; v < N; ++v) {
+      xs[v] += al[v] * ps[v];
+      rs[v] -= al[v] * qs[v];
+      const long row = (i * N + v) / T;
+      const V iv = row < n ? invd[row] : (V)0;
+      const double rd = (double)rs[v];
+      acc[0][v] += rd * rd * (double)iv;
+      acc[1][v] += rd * rd;
+    }
+    reinterpret_cast<VT*>(x)[i] = xv;
+    reinterpret_cast<VT*>(r)[i] = rv;
+  }
+  block_reduce_cols<kBS, 2, N>(acc, T, sh);
+  if (t < T) {
+    vals[t] = sh[t];
+    vals[T + t] = sh[kBS * N + t];
+  }
+  __syncthreads();
+  if (!grid_reduce<kBS>(vals, 2 * T, red)) return;
+  if (t < T) {
+    double be = 0.0;
+    if (cs->active[t]) {
+      const double rz = vals[t];
+      const double rr = vals[T + t];
+      cs->iters[t] += 1;
+      cs->it_cur[t] += 1;
+      if (rr <= rtol2 * cs->bnorm2[t]) {
+        cs->active[t] = 0;
+      } else if (cs->it_cur[t] >= max_iter) {
+        cs->active[t] = 0;
+        cs->status[t] = kStNoconv;
+        cs->oactive[t] = 0;
+      } else if (!(rz > 0.0) || !isfinite(rz)) {
+        cs->active[t] = 0;
+        cs->status[t] = kStBreak;
+        cs->oactive[t] = 0;
+      } else {
+        be = rz / cs->rho[t];
+        cs->rho[t] = rz;
+      }
+    }
+    cs->beta[t] = be;
+  }
+  recount_active(cs, T);
+}
+
+// p = D^-1 r + beta p
+template <typename V, int T>
+__global__ __launch_bounds__(kBS) void k_direction(int n, long cap, V* __restrict__ p,
+                                                   const V* __restrict__ r,
+                                                   const V* __restrict__ invd,
+                                                   const ColState* cs) {
+  using VT = typename Vec16<V>::type;
+  constexpr int N = Vec16<V>::N;
+  if (cs->n_active == 0) return;
+  const int t = threadIdx.x;
+  V be[N];
+#pragma unroll
+  for (int v = 0; v < N; ++v) be[v] = (V)cs->beta[(t * N + v) % T];
+  const long nv = cap / N;
+  for (long i = (long)blockIdx.x * kBS + t; i < nv; i += (long)gridDim.x * kBS) {
+    VT pv = reinterpret_cast<const VT*>(p)[i];
+    const VT rv = reinterpret_cast<const VT*>(r)[i];
+    V* ps = reinterpret_cast<V*>(&pv);
+    const V* rs = reinterpret_cast<const V*>(&rv);
+#pragma unroll
+    for (int v = 0; v < N; ++v) {
+      const long row = (i * N + v) / T;
+      const V iv = row < n ? invd[row] : (V)0;
+      ps[v] = rs[v] * iv + be[v] * ps[v];
+    }
+    reinterpret_cast<VT*>(p)[i] = pv;
+  }
+}
+
+// Inner (FP32) solve set-up from an FP64 vector src (the outer residual or
+// delta_bar): rbar = src - mean (FP64), r32 = rbar, p32 = D^-1 r32,
+// x32 = q32 = 0.
+// The last block checks outer convergence on ||rbar|| (FP64) and starts the
+// inner CG on the pairs that are still open.
+__global__ __launch_bounds__(kBS) void k_inner_init_any(int T, int n, long cap, const double* src,
+                                                        MeanSrc m, const float* invd32, float* x32,
+                                                        float* r32, float* p32, float* q32,
+                                                        double rtol2, int max_refine, int first,
+                                                        ColState* cs, GridRed red) {
+  __shared__ double sh[3 * kBS];
+  __shared__ double vals[3 * kMaxTile];
+  const int t = threadIdx.x;
+  double acc[3][1] = {{0.0}, {0.0}, {0.0}};
+  for (long e = (long)blockIdx.x * kBS + t; e < cap; e += (long)gridDim.x * kBS) {
+    const long i = e / T;
+    const int c = (int)(e % T);
+    float f = 0.0f;
+    float z = 0.0f;
+    if (i < n) {
+      const double v = src[e] - mean_of(m, i, c);
+      f = (float)v;
+      z = f * invd32[i];
+      acc[0][0] += v * v;
+      const double fd = (double)f;
+      acc[1][0] += fd * (double)z;
+      acc[2][0] += fd * fd;
+    }
+    r32[e] = f;
+    x32[e] = 0.0f;
+    p32[e] = z;                              // p0 = z0 = D^-1 r0
+    q32[e] = 0.0f;
+  }
+  block_reduce_cols<kBS, 3, 1>(acc, T, sh);
+  if (t < T) {
+    vals[t] = sh[t];
+    vals[T + t] = sh[kBS + t];
+    vals[2 * T + t] = sh[2 * kBS + t];
+  }
+  __syncthreads();
+  if (!grid_reduce<kBS>(vals, 3 * T, red)) return;
+  if (t < T) {
+    cs->orr[t] = vals[t];
+    int act = 0;
+    if (cs->oactive[t]) {
+      if (!first && vals[t] <= rtol2 * cs->obnorm2[t]) {
+        cs->oactive[t] = 0;
+      } else if (cs->refine[t] >= max_refine) {
+        cs->oactive[t] = 0;
+        cs->status[t] = kStNoconv;
+      } else if (vals[2 * T + t] > 0.0) {
+        act = 1;
+        cs->refine[t] += 1;
+      } else {
+        cs->oactive[t] = 0;   // residual rounds to zero in FP32: nothing left to add
+      }
+    }
+    cs->active[t] = act;
+    cs->bnorm2[t] = vals[2 * T + t];
+    cs->rho[t] = vals[T + t];
+    cs->it_cur[t] = 0;
+    cs->alpha[t] = 0.0;
+    cs->beta[t] = 0.0;
+  }
+  recount_active(cs, T);
+}
+
+// x64 += x32 (x32 is zero on pairs whose inner solve did not run; pairs
+// that failed keep their last good x).
+template <int T>
+__global__ __launch_bounds__(kBS) void k_accum(long cap, double* x64, const float* x32,
+                                               const ColState* cs) {
+  const int t = threadIdx.x;
+  for (long e = (long)blockIdx.x * kBS + t; e < cap; e += (long)gridDim.x * kBS) {
+    const int c = (int)(e % T);
+    if (cs->status[c] == kStOk) x64[e] += (double)x32[e];
+  }
+}
+
+// x -= mean (per component), optionally copied to the caller's X.
+template <int T>
+__global__ __launch_bounds__(kBS) void k_xfinal(int n, double* x64, MeanSrc m, double* X,
+                                                long ldx) {
+  const int t = threadIdx.x;
+  const long tot = (long)n * T;
+  for (long e = (long)blockIdx.x * kBS + t; e < tot; e += (long)gridDim.x * kBS) {
+    const long i = e / T;
+    const int c = (int)(e % T);
+    const double v = x64[e] - mean_of(m, i, c);
+    x64[e] = v;
+    if (X) X[i * ldx + c] = v;
+  }
+}
+
+// Warm start: x64 = X - mean is copied in (the caller's guess), b is kept.
+template <int T>
+__global__ __launch_bounds__(kBS) void k_xload(int n, double* x64, const double* X, long ldx) {
+  const int t = threadIdx.x;
+  const long tot = (long)n * T;
+  for (long e = (long)blockIdx.x * kBS + t; e < tot; e += (long)gridDim.x * kBS) {
+    const long i = e / T;
+    const int c = (int)(e % T);
+    x64[e] = X[i * ldx + c];
+  }
+}
+
+// FP64 restart from the true residual held in r64: p = D^-1 r, q = 0,
+// rho = r^T D^-1 r; CG resumes on the pairs still open.
+template <int T>
+__global__ __launch_bounds__(kBS) void k_restart(int n, long cap, const double* r64, double* p64,
+                                                 double* q64, const double* invd, ColState* cs,
+                                                 GridRed red) {
+  __shared__ double sh[kBS];
+  __shared__ double vals[kMaxTile];
+  const int t = threadIdx.x;
+  double acc[1][1] = {{0.0}};
+  for (long e = (long)blockIdx.x * kBS + t; e < cap; e += (long)gridDim.x * kBS) {
+    const long i = e / T;
+    double z = 0.0;
+    if (i < n) {
+      z = r64[e] * invd[i];
+      acc[0][0] += r64[e] * z;
+    }
+    p64[e] = z;                              // p0 = z0 = D^-1 r0
+    q64[e] = 0.0;
+  }
+  block_reduce_cols<kBS, 1, 1>(acc, T, sh);
+  if (t < T) vals[t] = sh[t];
+  __syncthreads();
+  if (!grid_reduce<kBS>(vals, T, red)) return;
+  if (t < T) {
+    cs->rho[t] = vals[t];
+    cs->active[t] = cs->oactive[t] && vals[t] > 0.0;
+    cs->bnorm2[t] = cs->obnorm2[t];
+    cs->it_cur[t] = 0;
+    cs->alpha[t] = 0.0;
+    cs->beta[t] = 0.0;
+  }
+  recount_active(cs, T);
+}
+
+// After a residual pass: open pairs are those whose true relative residual
+// is still above rtol (FP64 restart logic).
+__global__ void k_check(int T, double rtol2, ColState* cs) {
+  const int t = threadIdx.x;
+  if (t < T) {
+    const double rr = cs->dots[2][t];
+    cs->oactive[t] = (cs->status[t] == kStOk && cs->obnorm2[t] > 0.0 && rr > rtol2 * cs->obnorm2[t]);
+  }
+  recount_active(cs, T);
+}
+
+// d^2 = delta_bar^T x + x^T r from the last residual pass; d = sqrt(max(d^2, 0)).
+__global__ void k_finish(int T, int mark_open_noconv, ColState* cs, double* d_out,
+                         nvd_pair_info* info) {
+  const int t = threadIdx.x;
+  if (t >= T) return;
+  const double bx = cs->dots[0][t];
+  const double xr = cs->dots[1][t];
+  const double rr = cs->dots[2][t];
+  const double bb = cs->obnorm2[t];
+  double dsq = bx + xr;
+  double rel = 0.0;
+  if (bb > 0.0) {
+    rel = sqrt(rr / bb);
+  } else {
+    dsq = 0.0;
+  }
+  int st = cs->status[t];
+  if (mark_open_noconv && st == kStOk && cs->oactive[t]) st = kStNoconv;
+  d_out[t] = sqrt(dsq > 0.0 ? dsq : 0.0);
+  nvd_pair_info pi;
+  pi.status = st;
+  pi.iters = cs->iters[t];
+  pi.refine_steps = cs->refine[t];
+  pi.reserved = 0;
+  pi.rel_res = rel;
+  pi.dsq_plain = bb > 0.0 ? bx : 0.0;
+  pi.dsq = dsq;
+  info[t] = pi;
+}
+
+// delta_bar written to the caller's buffer (the stand-alone projection entry
+// point); norms[c] = ||delta_bar_c||.
+template <int T>
+__global__ __launch_bounds__(kBS) void k_proj_out(int n, ProjSrc src, MeanSrc m, double* D,
+                                                  long ldd, double* norms, GridRed red) {
+  __shared__ double sh[kBS];
+  __shared__ double vals[kMaxTile];
+  const int t = threadIdx.x;
+  double acc[1][1] = {{0.0}};
+  const long tot = (long)n * T;
+  for (long e = (long)blockIdx.x * kBS + t; e < tot; e += (long)gridDim.x * kBS) {
+    const long i = e / T;
+    const int c = (int)(e % T);
+    const double v = src.a[i * src.lda + c] - src.b[i * src.ldb + c] - mean_of(m, i, c);
+    D[i * ldd + c] = v;
+    acc[0][0] += v * v;
+  }
+  block_reduce_cols<kBS, 1, 1>(acc, T, sh);
+  if (t < T) vals[t] = sh[t];
+  __syncthreads();
+  if (!grid_reduce<kBS>(vals, T, red)) return;
+  if (t < T && norms) norms[t] = sqrt(vals[t]);
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+#define NVD_TILE_SWITCH(T, CALL)             \
+  switch (T) {                               \
+    case 1: { constexpr int TT = 1; CALL; } break;   \
+    case 2: { constexpr int TT = 2; CALL; } break;   \
+    case 4: { constexpr int TT = 4; CALL; } break;   \
+    case 8: { constexpr int TT = 8; CALL; } break;   \
+    case 16: { constexpr int TT = 16; CALL; } break; \
+    case 32: { constexpr int TT = 32; CALL; } break; \
+    case 64: { constexpr int TT = 64; CALL; } break; \
+    default: break;                          \
+  }
+
+static int stream_grid(long cap) {
+  long g = (cap + kBS - 1) / kBS;
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+static size_t padded_cap(int n, int T) { return (((size_t)n * T + 15) / 16) * 16; }
+
+static nvd_status poll(Workspace* ws, hipStream_t s, int* n_active, int* n_oactive) {
+  NVD_HIP(hipMemcpyAsync(ws->h_pinned, &ws->cs->n_active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  NVD_HIP(hipStreamSynchronize(s));
+  if (n_active) *n_active = ws->h_pinned[0];
+  if (n_oactive) *n_oactive = ws->h_pinned[1];
+  return NVD_OK;
+}
+
+// CG iterations until no column of the tile is active.
+template <typename V>
+static nvd_status cg_loop(DevGraph* g, Workspace* ws, int T, V* x, V* r, V* p, V* q,
+                          const V* invd, double rtol2, int max_iter, const SolveParams& sp,
+                          hipStream_t s) {
+  const long cap = (long)padded_cap(g->n, T);
+  const int sgrid = stream_grid(cap / Vec16<V>::N);
+  SpmmCall sc{};
+  sc.g = g;
+  sc.prec = sizeof(V) == 8 ? 0 : 1;
+  sc.T = T;
+  sc.nl = sp.nl;
+  sc.grid = sp.grid;
+  sc.x = p;
+  sc.ldx = T;
+  sc.y = q;
+  sc.ldy = T;
+  sc.cs = ws->cs;
+  sc.epi = EPI_CG;
+  const double sv = (double)sizeof(V);
+  const double upd_bytes = (6.0 * T * sv + sv) * g->n;   // x, r, p, q in; x, r out; 1/deg
+  const double dir_bytes = (3.0 * T * sv + sv) * g->n;   // r, p in; p out; 1/deg
+  int done = 0;
+  int chunk = 8;
+  while (done < max_iter) {
+    const int todo = std::min(chunk, max_iter - done);
+    for (int it = 0; it < todo; ++it) {
+      NVD_TRY(launch_spmm(sc, ws->red, s));
+      int pid = prof_begin(s, sizeof(V) == 8 ? PK_UPD64 : PK_UPD32, upd_bytes);
+      NVD_TILE_SWITCH(T, (k_update<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, x, r, p, q, invd, rtol2,
+                                                                max_iter, ws->cs, ws->red)));
+      prof_end(s, pid);
+      pid = prof_begin(s, sizeof(V) == 8 ? PK_DIR64 : PK_DIR32, dir_bytes);
+      NVD_TILE_SWITCH(T, (k_direction<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, p, r, invd, ws->cs)));
+      prof_end(s, pid);
+    }
+    NVD_HIP(hipGetLastError());
+    done += todo;
+    int na = 0;
+    NVD_TRY(poll(ws, s, &na, nullptr));
+    if (na == 0) break;
+    chunk = std::min(chunk * 2, 32);
+  }
+  return NVD_OK;
+}
+
+static nvd_status mean_into(DevGraph* g, Workspace* ws, int T, ProjSrc src, MeanSrc* m,
+                            hipStream_t s) {
+  *m = MeanSrc{};
+  m->n = g->n;
+  if (g->n_comp == 1) {
+    const int grid = stream_grid((long)g->n * T);
+    NVD_TILE_SWITCH(T, (k_colsum<TT><<<grid, kBS, 0, s>>>(g->n, src, ws->cs, ws->red)));
+    m->colmean = ws->cs->mean;
+  } else {
+    const int grid = std::min(g->n_comp, 4096);
+    NVD_TILE_SWITCH(T, (k_comp_mean<TT><<<grid, kBS, 0, s>>>(g->n_comp, g->comp_perm, g->comp_off,
+                                                            src, ws->comp_mean)));
+    m->cmean = ws->comp_mean;
+    m->comp = g->comp;
+  }
+  NVD_HIP(hipGetLastError());
+  return NVD_OK;
+}
+
+nvd_status project_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
+                        double* Dbar, int64_t ldd, double* norms, hipStream_t s) {
+  NVD_TRY(ensure_workspace(g, T, false));
+  Workspace* ws = g->ws;
+  MeanSrc m{};
+  NVD_TRY(mean_into(g, ws, T, ProjSrc{P, ld, Q, ld}, &m, s));
+  const int grid = stream_grid((long)g->n * T);
+  NVD_TILE_SWITCH(T, (k_proj_out<TT><<<grid, kBS, 0, s>>>(g->n, ProjSrc{P, ld, Q, ld}, m, Dbar, ldd,
+                                                          norms, ws->red)));
+  NVD_HIP(hipGetLastError());
+  return NVD_OK;
+}
+
+// Solve pairs [c0, c0+T) of the caller's P, Q.
+nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
+                      const SolveParams& sp, double* d_out, double* X, int64_t ldx,
+                      nvd_pair_info* info_dev, hipStream_t s) {
+  const bool mixed = sp.precision == NVD_MIXED;
+  NVD_TRY(ensure_workspace(g, T, mixed));
+  Workspace* ws = g->ws;
+  const int n = g->n;
+  const long cap = (long)padded_cap(n, T);
+  const int grid = stream_grid(cap);
+  const double rtol2 = sp.rtol * sp.rtol;
+
+  // (a2) delta_bar = (P - Q) minus its per-component mean
+  MeanSrc m{};
+  NVD_TRY(mean_into(g, ws, T, ProjSrc{P, ld, Q, ld}, &m, s));
+  NVD_TILE_SWITCH(T, (k_proj_init<TT><<<grid, kBS, 0, s>>>(
+                         n, cap, ProjSrc{P, ld, Q, ld}, m, g->invd64, ws->b64, ws->x64, ws->r64,
+                         ws->p64, ws->q64, mixed ? 0 : 1, ws->cs, ws->red)));
+  NVD_HIP(hipGetLastError());
+
+  SpmmCall resid{};
+  resid.g = g;
+  resid.prec = 0;
+  resid.T = T;
+  resid.nl = sp.nl;
+  resid.grid = sp.grid;
+  resid.x = ws->x64;
+  resid.ldx = T;
+  resid.y = ws->r64;
+  resid.ldy = T;
+  resid.b = ws->b64;
+  resid.ldb = T;
+  resid.cs = ws->cs;
+  resid.epi = EPI_RESID;
+
+  bool have_x = false;
+  if (sp.warm && X) {
+    NVD_TILE_SWITCH(T, (k_xload<TT><<<grid, kBS, 0, s>>>(n, ws->x64, X, ldx)));
+    NVD_HIP(hipGetLastError());
+    have_x = true;
+  }
+
+  if (!mixed) {
+    if (have_x) {
+      // r = delta_bar - L x0, then CG from there
+      NVD_TRY(launch_spmm(resid, ws->red, s));
+      NVD_TILE_SWITCH(T, (k_restart<TT><<<grid, kBS, 0, s>>>(n, cap, ws->r64, ws->p64, ws->q64,
+                                                             g->invd64, ws->cs, ws->red)));
+      NVD_HIP(hipGetLastError());
+    }
+    int restarts = 0;
+    for (;;) {
+      NVD_TRY(cg_loop<double>(g, ws, T, ws->x64, ws->r64, ws->p64, ws->q64, g->invd64, rtol2,
+                              sp.max_iter, sp, s));
+      // x mean-zero, true residual, restart if needed
+      MeanSrc mx{};
+      NVD_TRY(mean_into(g, ws, T, ProjSrc{ws->x64, T, nullptr, 0}, &mx, s));
+      NVD_TILE_SWITCH(T, (k_xfinal<TT><<<grid, kBS, 0, s>>>(n, ws->x64, mx, nullptr, 0)));
+      NVD_TRY(launch_spmm(resid, ws->red, s));
+      k_check<<<1, 64, 0, s>>>(T, rtol2, ws->cs);
+      NVD_HIP(hipGetLastError());
+      int no = 0;
+      NVD_TRY(poll(ws, s, nullptr, &no));
+      if (no == 0 || restarts >= 2) break;
+      ++restarts;
+      NVD_TILE_SWITCH(T, (k_restart<TT><<<grid, kBS, 0, s>>>(n, cap, ws->r64, ws->p64, ws->q64,
+                                                             g->invd64, ws->cs, ws->red)));
+      NVD_HIP(hipGetLastError());
+    }
+  } else {
+    const double irtol2 = sp.inner_rtol * sp.inner_rtol;
+    bool first = !have_x;
+    for (int step = 0; step <= sp.max_refine; ++step) {
+      MeanSrc mr{};
+      const double* src = ws->b64;
+      if (!first) {
+        // (a7) FP64 outer residual r = delta_bar - L x, projected
+        NVD_TRY(launch_spmm(resid, ws->red, s));
+        if (g->n_comp == 1) {
+          mr.n = n;
+          mr.dots_sum = ws->cs->dots[3];
+        } else {
+          NVD_TRY(mean_into(g, ws, T, ProjSrc{ws->r64, T, nullptr, 0}, &mr, s));
+        }
+        src = ws->r64;
+      }
+      k_inner_init_any<<<grid, kBS, 0, s>>>(T, n, cap, src, mr, g->invd32, ws->x32, ws->r32,
+                                            ws->p32, ws->q32, rtol2, sp.max_refine, first ? 1 : 0,
+                                            ws->cs, ws->red);
+      NVD_HIP(hipGetLastError());
+      first = false;
+      int no = 0;
+      NVD_TRY(poll(ws, s, nullptr, &no));
+      if (no == 0) break;
+      NVD_TRY(cg_loop<float>(g, ws, T, ws->x32, ws->r32, ws->p32, ws->q32, g->invd32, irtol2,
+                             sp.max_iter, sp, s));
+      NVD_TILE_SWITCH(T, (k_accum<TT><<<grid, kBS, 0, s>>>(cap, ws->x64, ws->x32, ws->cs)));
+      NVD_HIP(hipGetLastError());
+    }
+    MeanSrc mx{};
+    NVD_TRY(mean_into(g, ws, T, ProjSrc{ws->x64, T, nullptr, 0}, &mx, s));
+    NVD_TILE_SWITCH(T, (k_xfinal<TT><<<grid, kBS, 0, s>>>(n, ws->x64, mx, nullptr, 0)));
+    NVD_TRY(launch_spmm(resid, ws->red, s));
+  }
+  // (a8) quadratic form, distances, per-pair info; copy x out
+  if (X) {
+    MeanSrc none{};
+    none.n = n;
+    NVD_TILE_SWITCH(T, (k_xfinal<TT><<<grid, kBS, 0, s>>>(n, ws->x64, none, X, ldx)));
+  }
+  k_finish<<<1, 64, 0, s>>>(T, mixed ? 0 : 1, ws->cs, d_out, info_dev);
+  NVD_HIP(hipGetLastError());
+  return NVD_OK;
+}
+
+}  // namespace nvd

@@ -1,0 +1,194 @@
+// Internal declarations shared by the library's translation units.
+// Device side: per-column solver state, grid-wide deterministic reductions,
+// block reductions by column.  Host side: the graph handle, workspace and
+// error plumbing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/nvd.h"
+
+namespace nvd {
+
+// ---------------------------------------------------------------------------
+// limits and tuning constants
+// ---------------------------------------------------------------------------
+constexpr int kMaxTile = 64;        // columns per SpMM pass / solver tile
+constexpr int kBS = 256;            // threads per block for the streaming kernels
+constexpr int kGrp = 32;            // blocks per first-level reduction group
+constexpr int kMaxBlocks = 4096;    // grid cap for kernels that reduce
+constexpr int kMaxDots = 6;         // dot products reduced by one kernel
+constexpr int kLongRow = 128;       // rows with more neighbours take the split-row path
+constexpr int kSeg = 2048;          // neighbours per split-row segment
+
+// per-column status codes (match nvd_status)
+constexpr int kStOk = NVD_OK;
+constexpr int kStNoconv = NVD_E_NOCONV;
+constexpr int kStBreak = NVD_E_BREAKDOWN;
+
+// ---------------------------------------------------------------------------
+// per-column solver state for one tile (device memory)
+// ---------------------------------------------------------------------------
+struct ColState {
+  double rho[kMaxTile];     // r^T z of the running CG
+  double alpha[kMaxTile];
+  double beta[kMaxTile];
+  double bnorm2[kMaxTile];  // ||rhs||^2 of the running CG
+  double obnorm2[kMaxTile]; // ||delta_bar||^2 (outer right-hand side)
+  double orr[kMaxTile];     // latest outer ||r||^2 (projected, FP64)
+  double mean[kMaxTile];    // mean removed by the last projection (1 component)
+  double dots[kMaxDots][kMaxTile];  // dots of the last residual pass
+  int active[kMaxTile];     // running CG still iterating
+  int oactive[kMaxTile];    // pair not yet converged (outer level)
+  int iters[kMaxTile];      // CG iterations, summed over inner solves
+  int it_cur[kMaxTile];     // iterations of the running CG
+  int status[kMaxTile];
+  int refine[kMaxTile];
+  int n_active;             // count of active[] (host polls this)
+  int n_oactive;
+  int pad[2];
+};
+
+// Two-level, fixed-order grid reduction scratch.
+struct GridRed {
+  double* part1;     // [kMaxBlocks][kMaxDots*kMaxTile]
+  double* part2;     // [kMaxBlocks/kGrp][kMaxDots*kMaxTile]
+  unsigned* tick1;   // [kMaxBlocks/kGrp]
+  unsigned* tick2;   // [1]
+};
+
+// Split-row (long row) work list for the SpMM.
+struct LongRows {
+  int n_seg = 0;         // total segments (one block each)
+  const int* seg_row = nullptr;    // row of segment s
+  const int* seg_lo = nullptr;     // nnz range [lo, hi) of segment s
+  const int* seg_hi = nullptr;
+  const int* seg_first = nullptr;  // first segment of that row
+  const int* seg_cnt = nullptr;    // segments of that row
+  double* seg_part = nullptr;      // [n_seg][kMaxTile] partial sums
+  unsigned* row_tick = nullptr;    // [n_seg] arrival counters (indexed by first seg)
+};
+
+// ---------------------------------------------------------------------------
+// host-side handles
+// ---------------------------------------------------------------------------
+struct Workspace;
+
+struct DevGraph {
+  int n = 0;
+  int nnz = 0;                 // internal nnz (self-loops removed)
+  int64_t nnz_in = 0;          // nnz as passed in
+  bool weighted = false;
+  int n_comp = 0;
+  int n_isolated = 0;
+  int max_deg = 0;
+  int self_loops = 0;
+  // device arrays
+  int* rp = nullptr;           // [n+1]
+  int* ci = nullptr;           // [nnz]
+  double* w64 = nullptr;       // [nnz] or null (unit)
+  float* w32 = nullptr;
+  double* deg64 = nullptr;     // [n]
+  float* deg32 = nullptr;
+  double* invd64 = nullptr;    // [n], 0 for isolated nodes
+  float* invd32 = nullptr;
+  int* comp = nullptr;         // [n] component label
+  int* comp_perm = nullptr;    // nodes grouped by component
+  int* comp_off = nullptr;     // [n_comp+1]
+  int* in_pos = nullptr;       // [nnz] input position of each internal entry (null if identity)
+  int* long_buf = nullptr;     // segment arrays
+  LongRows lr;
+  int n_long_rows = 0;
+  // host copies kept for queries and batching
+  std::vector<int> h_rp, h_ci, h_comp;
+  std::vector<double> h_w;     // empty if unit
+  int64_t bytes = 0;
+  Workspace* ws = nullptr;
+  int tuned_tile[2][8] = {};   // [precision][log2 k bucket] -> tile (0 = not tuned)
+};
+
+struct Workspace {
+  size_t cap_rows = 0;         // rows * tile capacity (elements per vector)
+  int cap_tile = 0;
+  // FP64 vectors (n x tile)
+  double* b64 = nullptr;       // delta_bar
+  double* x64 = nullptr;
+  double* r64 = nullptr;
+  double* p64 = nullptr;
+  double* q64 = nullptr;
+  // FP32 vectors for the inner solver
+  float* x32 = nullptr;
+  float* r32 = nullptr;
+  float* p32 = nullptr;
+  float* q32 = nullptr;
+  double* comp_mean = nullptr; // [n_comp][kMaxTile]
+  ColState* cs = nullptr;
+  GridRed red{};
+  int* h_pinned = nullptr;     // pinned host words for polling
+  int64_t bytes = 0;
+};
+
+// ---------------------------------------------------------------------------
+// error plumbing (host)
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+const char* get_error();
+
+#define NVD_HIP(call)                                                     \
+  do {                                                                    \
+    hipError_t e_ = (call);                                               \
+    if (e_ != hipSuccess) {                                               \
+      ::nvd::set_error(std::string(#call) + ": " + hipGetErrorString(e_)); \
+      return e_ == hipErrorOutOfMemory ? NVD_E_NOMEM : NVD_E_DEVICE;     \
+    }                                                                     \
+  } while (0)
+
+#define NVD_TRY(expr)                  \
+  do {                                 \
+    nvd_status s_ = (expr);            \
+    if (s_ != NVD_OK) return s_;       \
+  } while (0)
+
+// workspace management (graph.hip)
+nvd_status ensure_workspace(DevGraph* g, int tile, bool need32);
+nvd_status free_workspace(Workspace* ws);
+
+// kernels' host launchers (spmm.hip, cg.hip)
+enum Epi { EPI_PLAIN = 0, EPI_CG = 1, EPI_RESID = 2 };
+
+struct SpmmCall {
+  const DevGraph* g;
+  int prec;                 // 0: FP64 weights/vectors, 1: FP32
+  int T;                    // columns
+  int nl;                   // lanes per row across neighbours (0 = auto)
+  const void* x; int64_t ldx;
+  void* y; int64_t ldy;
+  const double* b; int64_t ldb;   // EPI_RESID right-hand side
+  ColState* cs;
+  int epi;
+  int grid;                 // short-row blocks (0 = auto)
+};
+nvd_status launch_spmm(const SpmmCall& c, const GridRed& red, hipStream_t s);
+
+struct SolveParams {
+  int precision;            // NVD_FP64 or NVD_MIXED
+  double rtol, inner_rtol;
+  int max_iter, max_refine;
+  int nl;                   // SpMM lanes per row across neighbours (0 = default)
+  int grid;                 // SpMM short-row grid (0 = default)
+  bool warm;
+};
+nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
+                      const SolveParams& sp, double* d_out, double* X, int64_t ldx,
+                      nvd_pair_info* info_dev, hipStream_t s);
+nvd_status project_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
+                        double* Dbar, int64_t ldd, double* norms, hipStream_t s);
+int choose_tile(DevGraph* g, int k, int precision, hipStream_t s);
+int default_nl(int T);
+int default_short_grid(int n, int T, int nl);
+
+}  // namespace nvd
