@@ -240,19 +240,18 @@ nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double*
   sp.warm = (o.flags & NVD_WARM_START) != 0;
   int tile = o.tile_k;
   if (tile == 0) tile = choose_tile(g, k, o.precision, s);
-  // device buffer for the per-pair info of one tile
-  nvd_pair_info* info_dev = nullptr;
-  NVD_HIP(hipMalloc((void**)&info_dev, sizeof(nvd_pair_info) * kMaxTile));
   std::vector<nvd_pair_info> hinfo(k);
   nvd_status agg = NVD_OK;
   nvd_status st = NVD_OK;
   for (int c0 = 0; c0 < k && st == NVD_OK;) {
     int T = tile;
     while (T > k - c0) T >>= 1;
-    st = solve_tile(g, T, P + c0, Q + c0, ld, sp, d_out + c0, X ? X + c0 : nullptr, ldx,
-                    info_dev, s);
+    st = ensure_workspace(g, T, o.precision == NVD_MIXED);
+    if (st == NVD_OK)
+      st = solve_tile(g, T, P + c0, Q + c0, ld, sp, d_out + c0, X ? X + c0 : nullptr, ldx,
+                      g->ws->info, s);
     if (st == NVD_OK) {
-      hipError_t e = hipMemcpyAsync(hinfo.data() + c0, info_dev, sizeof(nvd_pair_info) * T,
+      hipError_t e = hipMemcpyAsync(hinfo.data() + c0, g->ws->info, sizeof(nvd_pair_info) * T,
                                     hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) {
@@ -262,7 +261,6 @@ nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double*
     }
     c0 += T;
   }
-  (void)hipFree(info_dev);
   if (st != NVD_OK) return st;
   for (int j = 0; j < k; ++j) {
     if (hinfo[j].status == NVD_E_BREAKDOWN) agg = NVD_E_BREAKDOWN;

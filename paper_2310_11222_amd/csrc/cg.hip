@@ -151,6 +151,28 @@ __global__ __launch_bounds__(kBS) void k_proj_init(int n, long cap, ProjSrc src,
   recount_active(cs, T);
 }
 
+// 1/deg for the N elements of vector i (row-major n x T, N elements per
+// 16-byte vector).  When T >= N all N elements share one row: one load.
+// Otherwise the N rows are loaded with clamped indices (no branch per load)
+// and zeroed past n.
+template <typename V, int T>
+__device__ __forceinline__ void invd_of(const V* __restrict__ invd, int n, long i, V (&iv)[Vec16<V>::N]) {
+  constexpr int N = Vec16<V>::N;
+  if constexpr (T >= N) {
+    const long row = (i * N) / T;
+    const V v = invd[row < n ? row : n - 1];
+#pragma unroll
+    for (int k = 0; k < N; ++k) iv[k] = row < n ? v : (V)0;
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const long row = (i * N + k) / T;
+      const V v = invd[row < n ? row : n - 1];
+      iv[k] = row < n ? v : (V)0;
+    }
+  }
+}
+
 // x += alpha p; r -= alpha q; rho' = r^T D^-1 r; ||r||^2.  The grid's last
 // block forms beta and retires converged columns.
 template <typename V, int T>
@@ -181,14 +203,14 @@ __global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__
     V* rs = reinterpret_cast<V*>(&rv);
     const V* ps = reinterpret_cast<const V*>(&pv);
     const V* qs = reinterpret_cast<const V*>(&qv);
+    V iv[N];
+    invd_of<V, T>(invd, n, i, iv);
 #pragma unroll
     for (int v = 0; v < N; ++v) {
       xs[v] += al[v] * ps[v];
       rs[v] -= al[v] * qs[v];
-      const long row = (i * N + v) / T;
-      const V iv = row < n ? invd[row] : (V)0;
       const double rd = (double)rs[v];
-      acc[0][v] += rd * rd * (double)iv;
+      acc[0][v] += rd * rd * (double)iv[v];
       acc[1][v] += rd * rd;
     }
     reinterpret_cast<VT*>(x)[i] = xv;
@@ -247,12 +269,10 @@ __global__ __launch_bounds__(kBS) void k_direction(int n, long cap, V* __restric
     const VT rv = reinterpret_cast<const VT*>(r)[i];
     V* ps = reinterpret_cast<V*>(&pv);
     const V* rs = reinterpret_cast<const V*>(&rv);
+    V iv[N];
+    invd_of<V, T>(invd, n, i, iv);
 #pragma unroll
-    for (int v = 0; v < N; ++v) {
-      const long row = (i * N + v) / T;
-      const V iv = row < n ? invd[row] : (V)0;
-      ps[v] = rs[v] * iv + be[v] * ps[v];
-    }
+    for (int v = 0; v < N; ++v) ps[v] = rs[v] * iv[v] + be[v] * ps[v];
     reinterpret_cast<VT*>(p)[i] = pv;
   }
 }

@@ -40,52 +40,96 @@ __device__ __forceinline__ void block_reduce_cols(const double (&acc)[ND][NE],
   }
 }
 
+// Wait until this thread's outstanding memory operations have completed.
+// Partials are written with agent-scope (coherent) stores; once they have
+// completed they are visible to every XCD, so publishing them needs no L2
+// write-back fence -- a full agent-scope fence per block would write back the
+// whole L2 of the XCD, including the kernel's streaming output.
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0); }
+
+__device__ __forceinline__ unsigned ticket(unsigned* p) {
+  return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum `count` rows (row stride kRedStride) of ndt values from src into
+// dst[ndt] in a fixed order that does not depend on timing: thread t takes
+// entry i = t % ndt of rows s, s + ns, ... (s = t / ndt, ns slices), then the
+// slices are added in slice order.  Loads are agent-scope (coherent) loads.
+template <int BS>
+__device__ __forceinline__ void sum_rows_fixed(const double* src, int count, int ndt,
+                                               double* red /* LDS [BS] */, double* dst) {
+  const int t = threadIdx.x;
+  if (ndt * 2 <= BS) {
+    int ns = BS / ndt;
+    if (ns > count) ns = count;
+    const int s = t / ndt;
+    const int i = t - s * ndt;
+    if (s < ns) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int j = s;
+      for (; j + 3 * ns < count; j += 4 * ns) {
+        a0 += ld_agent(src + (size_t)j * kRedStride + i);
+        a1 += ld_agent(src + (size_t)(j + ns) * kRedStride + i);
+        a2 += ld_agent(src + (size_t)(j + 2 * ns) * kRedStride + i);
+        a3 += ld_agent(src + (size_t)(j + 3 * ns) * kRedStride + i);
+      }
+      for (; j < count; j += ns) a0 += ld_agent(src + (size_t)j * kRedStride + i);
+      red[s * ndt + i] = (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+    if (t < ndt) {
+      double tot = 0.0;
+      for (int q = 0; q < ns; ++q) tot += red[q * ndt + t];
+      dst[t] = tot;
+    }
+    __syncthreads();
+  } else {
+    for (int i = t; i < ndt; i += BS) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int j = 0;
+      for (; j + 3 < count; j += 4) {
+        a0 += ld_agent(src + (size_t)j * kRedStride + i);
+        a1 += ld_agent(src + (size_t)(j + 1) * kRedStride + i);
+        a2 += ld_agent(src + (size_t)(j + 2) * kRedStride + i);
+        a3 += ld_agent(src + (size_t)(j + 3) * kRedStride + i);
+      }
+      for (; j < count; ++j) a0 += ld_agent(src + (size_t)j * kRedStride + i);
+      dst[i] = (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+  }
+}
+
 // Grid-wide reduction of ndt = ND*T values per block (vals, in LDS).  Blocks
 // form groups of kGrp; the last block to arrive in a group sums the group's
-// partials in block order, and the last group to finish sums the group
-// results in group order.  Returns true in exactly one block, whose vals then
-// hold the grid totals.  Every block of the grid must call it.
+// partials, and the last group to finish sums the group results, both with
+// sum_rows_fixed (fixed order, so results repeat bit for bit).  Returns true
+// in exactly one block, whose vals then hold the grid totals.  Every block of
+// the grid must call it.
 template <int BS>
 __device__ bool grid_reduce(double* vals, int ndt, const GridRed& red) {
   __shared__ int s_last;
+  __shared__ double s_red[BS];
   const int b = blockIdx.x;
   const int nb = gridDim.x;
   const int grp = b / kGrp;
   const int ngrp = (nb + kGrp - 1) / kGrp;
   const int gsz = min(kGrp, nb - grp * kGrp);
-  const int stride = kMaxDots * kMaxTile;
-  for (int i = threadIdx.x; i < ndt; i += BS) st_agent(&red.part1[(size_t)b * stride + i], vals[i]);
-  __threadfence();
+  for (int i = threadIdx.x; i < ndt; i += BS) st_agent(&red.part1[(size_t)b * kRedStride + i], vals[i]);
+  wait_stores();
   __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned t = atomicAdd(&red.tick1[grp], 1u);
-    s_last = (t == (unsigned)(gsz - 1));
-  }
+  if (threadIdx.x == 0) s_last = (ticket(&red.tick1[grp]) == (unsigned)(gsz - 1));
   __syncthreads();
   if (!s_last) return false;
-  __threadfence();
-  for (int i = threadIdx.x; i < ndt; i += BS) {
-    double s = 0.0;
-    const double* p = red.part1 + (size_t)grp * kGrp * stride + i;
-    for (int j = 0; j < gsz; ++j) s += ld_agent(p + (size_t)j * stride);
-    st_agent(&red.part2[(size_t)grp * stride + i], s);
-  }
+  sum_rows_fixed<BS>(red.part1 + (size_t)grp * kGrp * kRedStride, gsz, ndt, s_red, vals);
+  for (int i = threadIdx.x; i < ndt; i += BS) st_agent(&red.part2[(size_t)grp * kRedStride + i], vals[i]);
   if (threadIdx.x == 0) red.tick1[grp] = 0u;
-  __threadfence();
+  wait_stores();
   __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned t = atomicAdd(red.tick2, 1u);
-    s_last = (t == (unsigned)(ngrp - 1));
-  }
+  if (threadIdx.x == 0) s_last = (ticket(red.tick2) == (unsigned)(ngrp - 1));
   __syncthreads();
   if (!s_last) return false;
-  __threadfence();
-  for (int i = threadIdx.x; i < ndt; i += BS) {
-    double s = 0.0;
-    const double* p = red.part2 + i;
-    for (int j = 0; j < ngrp; ++j) s += ld_agent(p + (size_t)j * stride);
-    vals[i] = s;
-  }
+  sum_rows_fixed<BS>(red.part2, ngrp, ndt, s_red, vals);
   if (threadIdx.x == 0) *red.tick2 = 0u;
   __syncthreads();
   return true;

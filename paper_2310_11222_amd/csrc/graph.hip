@@ -59,7 +59,7 @@ static void free_graph_arrays(DevGraph* g) {
 nvd_status free_workspace(Workspace* ws) {
   if (!ws) return NVD_OK;
   void* ptrs[] = {ws->b64, ws->x64, ws->r64, ws->p64, ws->q64, ws->x32, ws->r32, ws->p32,
-                  ws->q32, ws->comp_mean, ws->cs, ws->red.part1, ws->red.part2,
+                  ws->q32, ws->comp_mean, ws->cs, ws->info, ws->red.part1, ws->red.part2,
                   ws->red.tick1, ws->red.tick2};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -103,7 +103,8 @@ nvd_status ensure_workspace(DevGraph* g, int tile, bool need32) {
   }
   chk(dalloc(&ws->comp_mean, (size_t)std::max(g->n_comp, 1) * kMaxTile, by));
   chk(dalloc(&ws->cs, 1, by));
-  const size_t stride = kMaxDots * kMaxTile;
+  chk(dalloc(&ws->info, kMaxTile, by));
+  const size_t stride = kRedStride;
   chk(dalloc(&ws->red.part1, (size_t)kMaxBlocks * stride, by));
   chk(dalloc(&ws->red.part2, (size_t)(kMaxBlocks / kGrp) * stride, by));
   chk(dalloc(&ws->red.tick1, (size_t)(kMaxBlocks / kGrp), by));

@@ -22,6 +22,7 @@ constexpr int kBS = 256;            // threads per block for the streaming kerne
 constexpr int kGrp = 32;            // blocks per first-level reduction group
 constexpr int kMaxBlocks = 4096;    // grid cap for kernels that reduce
 constexpr int kMaxDots = 6;         // dot products reduced by one kernel
+constexpr int kRedStride = kMaxDots * 64;  // doubles per block in the reduction scratch
 constexpr int kLongRow = 128;       // rows with more neighbours take the split-row path
 constexpr int kSeg = 2048;          // neighbours per split-row segment
 
@@ -127,6 +128,7 @@ struct Workspace {
   float* q32 = nullptr;
   double* comp_mean = nullptr; // [n_comp][kMaxTile]
   ColState* cs = nullptr;
+  nvd_pair_info* info = nullptr;  // [kMaxTile] per-pair results of one tile
   GridRed red{};
   int* h_pinned = nullptr;     // pinned host words for polling
   int64_t bytes = 0;

@@ -4,8 +4,10 @@
 //
 // Work split:
 //  * short rows (<= kLongRow neighbours): a group of G = T*NL lanes per row;
-//    lane (c, j) owns column c and walks neighbours j, j+NL, ...; the NL
-//    partial sums meet by cross-lane shuffles.  A wave holds 64/G rows.
+//    lane (c, j) owns column c and takes neighbours j, j+NL, ...; neighbour
+//    indices are loaded G at a time by the whole group and shuffled out, so
+//    the gathers of x issue back to back; the NL partial sums meet by
+//    cross-lane shuffles.  A wave holds 64/G rows.
 //  * long rows: segments of at most kSeg neighbours, one 256-thread block per
 //    segment (256/T lanes per column), partial sums reduced in LDS; rows with
 //    several segments combine them in fixed order in the last segment block
@@ -40,14 +42,8 @@ struct SpmmK {
 };
 
 template <typename V, bool UNIT, int EPI, int ND>
-__device__ __forceinline__ void spmm_epilogue(const SpmmK<V>& a, int row, int c,
-                                              V sum, double (&acc)[ND][1]) {
-  const V own = a.x[(long)row * a.ldx + c];
-  V dg;
-  if constexpr (UNIT)
-    dg = (V)(a.rp[row + 1] - a.rp[row]);
-  else
-    dg = a.deg[row];
+__device__ __forceinline__ void spmm_epilogue(const SpmmK<V>& a, int row, int c, V sum, V own,
+                                              V dg, double bb, double (&acc)[ND][1]) {
   const V yv = dg * own - sum;
   if constexpr (EPI == EPI_PLAIN) {
     a.y[(long)row * a.ldy + c] = yv;
@@ -55,7 +51,6 @@ __device__ __forceinline__ void spmm_epilogue(const SpmmK<V>& a, int row, int c,
     a.y[(long)row * a.ldy + c] = yv;
     acc[0][0] += (double)own * (double)yv;
   } else {
-    const double bb = a.b[(long)row * a.ldb + c];
     const double rr = bb - (double)yv;
     a.y[(long)row * a.ldy + c] = (V)rr;
     acc[0][0] += bb * (double)own;
@@ -65,6 +60,26 @@ __device__ __forceinline__ void spmm_epilogue(const SpmmK<V>& a, int row, int c,
     acc[4][0] += (double)own;
   }
 }
+
+template <typename V, bool UNIT, int EPI, int ND>
+__device__ __forceinline__ void spmm_epilogue_load(const SpmmK<V>& a, int row, int c, V sum,
+                                                   double (&acc)[ND][1]) {
+  const V own = a.x[(long)row * a.ldx + c];
+  V dg;
+  if constexpr (UNIT)
+    dg = (V)(a.rp[row + 1] - a.rp[row]);
+  else
+    dg = a.deg[row];
+  double bb = 0.0;
+  if constexpr (EPI == EPI_RESID) bb = a.b[(long)row * a.ldb + c];
+  spmm_epilogue<V, UNIT, EPI, ND>(a, row, c, sum, own, dg, bb, acc);
+}
+
+// Rows carried at once by one lane group (short-row path).
+template <typename V, int T>
+struct SpmmRows {
+  static constexpr int R = (sizeof(V) == 8 && T >= 32) ? 2 : 4;
+};
 
 template <typename V, int T, int NL, bool UNIT, int EPI>
 __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows lr) {
@@ -110,22 +125,18 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
       const int first = lr.seg_first[s];
       const int cnt = lr.seg_cnt[s];
       if (cnt == 1) {
-        if (t < T) spmm_epilogue<V, UNIT, EPI, NDA>(a, row, t, (V)sh_long[t], acc);
+        if (t < T) spmm_epilogue_load<V, UNIT, EPI, NDA>(a, row, t, (V)sh_long[t], acc);
       } else {
         if (t < T) st_agent(&lr.seg_part[(long)s * kMaxTile + t], sh_long[t]);
-        __threadfence();
+        wait_stores();
         __syncthreads();
-        if (t == 0) {
-          unsigned k = atomicAdd(&lr.row_tick[first], 1u);
-          s_last = (k == (unsigned)(cnt - 1));
-        }
+        if (t == 0) s_last = (ticket(&lr.row_tick[first]) == (unsigned)(cnt - 1));
         __syncthreads();
         if (s_last) {
-          __threadfence();
           if (t < T) {
             double tot = 0.0;
             for (int i = 0; i < cnt; ++i) tot += ld_agent(&lr.seg_part[(long)(first + i) * kMaxTile + t]);
-            spmm_epilogue<V, UNIT, EPI, NDA>(a, row, t, (V)tot, acc);
+            spmm_epilogue_load<V, UNIT, EPI, NDA>(a, row, t, (V)tot, acc);
           }
           if (t == 0) lr.row_tick[first] = 0u;
         }
@@ -134,7 +145,9 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
     }
   } else {
     // ---- short rows.  Blocks are renumbered so that each XCD (blocks are
-    // dealt to the 8 XCDs round-robin) walks contiguous row ranges.
+    // dealt to the 8 XCDs round-robin) walks contiguous row ranges.  Each
+    // lane group carries R rows at once: their row bounds, neighbour indices,
+    // gathers and own values are all issued before any of them is waited on.
     const int nsb = a.nshort_blocks;
     int sb = (int)blockIdx.x - a.nlong_blocks;
     if ((nsb & 7) == 0) sb = (sb & 7) * (nsb >> 3) + (sb >> 3);
@@ -144,28 +157,89 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
     const int li = lane % G;
     const int c = li % T;
     const int j = li / T;
-    constexpr int ROWS_PER_STEP = (kBS / 64) * RW;
+    constexpr int R = SpmmRows<V, T>::R;
+    constexpr int ROWS_PER_WAVE = RW * R;
+    constexpr int ROWS_PER_STEP = (kBS / 64) * ROWS_PER_WAVE;
+    constexpr int MM = G / NL;             // neighbours per lane per chunk (= T)
+    constexpr int MB = MM < 8 ? MM : 8;
     for (int base = sb * ROWS_PER_STEP; base < a.n; base += nsb * ROWS_PER_STEP) {
-      const int row = base + wave * RW + g;
-      if (row < a.n) {
-        const int rs = a.rp[row];
-        const int re = a.rp[row + 1];
-        if (re - rs <= kLongRow) {
-          V sum = (V)0;
-#pragma unroll 4
-          for (int e = rs + j; e < re; e += NL) {
-            const int col = a.ci[e];
-            V wt;
-            if constexpr (UNIT)
-              wt = (V)1;
-            else
-              wt = a.w[e];
-            sum += wt * a.x[(long)col * a.ldx + c];
+      int row[R], rs[R], deg[R];
+      bool mine[R];
+      V own[R], dg[R];
+      double bb[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        row[r] = base + wave * ROWS_PER_WAVE + r * RW + g;
+        rs[r] = 0;
+        deg[r] = -1;                        // -1: no row in this slot
+        if (row[r] < a.n) {
+          rs[r] = a.rp[row[r]];
+          deg[r] = a.rp[row[r] + 1] - rs[r];
+        }
+      }
+      int maxdeg = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        mine[r] = deg[r] >= 0 && deg[r] <= kLongRow;
+        own[r] = mine[r] ? a.x[(long)row[r] * a.ldx + c] : (V)0;
+        if constexpr (UNIT)
+          dg[r] = (V)(deg[r] > 0 ? deg[r] : 0);
+        else
+          dg[r] = mine[r] ? a.deg[row[r]] : (V)0;
+        bb[r] = 0.0;
+        if constexpr (EPI == EPI_RESID) bb[r] = mine[r] ? a.b[(long)row[r] * a.ldb + c] : 0.0;
+        if (!mine[r]) deg[r] = 0;
+        maxdeg = deg[r] > maxdeg ? deg[r] : maxdeg;
+      }
+      V sum[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) sum[r] = (V)0;
+      for (int off = 0; off < maxdeg; off += G) {          // uniform across the group
+        int myc[R], cnt[R];
+        V myw[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          cnt[r] = deg[r] - off;
+          cnt[r] = cnt[r] < 0 ? 0 : (cnt[r] > G ? G : cnt[r]);
+          myc[r] = li < cnt[r] ? a.ci[rs[r] + off + li] : 0;
+          myw[r] = (V)1;
+          if constexpr (!UNIT) myw[r] = li < cnt[r] ? a.w[rs[r] + off + li] : (V)0;
+        }
+        int maxcnt = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) maxcnt = cnt[r] > maxcnt ? cnt[r] : maxcnt;
+#pragma unroll
+        for (int m0 = 0; m0 < MM; m0 += MB) {
+          if (NL * m0 >= maxcnt) break;                    // uniform across the group
+          V xv[R][MB];
+          V wv[R][MB];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+              const int idx = j + NL * (m0 + m);
+              const int col = __shfl(myc[r], idx, G);
+              if constexpr (UNIT)
+                wv[r][m] = (V)1;
+              else
+                wv[r][m] = __shfl(myw[r], idx, G);
+              xv[r][m] = idx < cnt[r] ? a.x[(long)col * a.ldx + c] : (V)0;
+            }
           }
 #pragma unroll
-          for (int off = T; off < G; off <<= 1) sum += __shfl_xor(sum, off, 64);
-          if (j == 0) spmm_epilogue<V, UNIT, EPI, NDA>(a, row, c, sum, acc);
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int m = 0; m < MB; ++m) sum[r] += wv[r][m] * xv[r][m];
         }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int off = T; off < G; off <<= 1) sum[r] += __shfl_xor(sum[r], off, 64);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (j == 0 && mine[r]) spmm_epilogue<V, UNIT, EPI, NDA>(a, row[r], c, sum[r], own[r], dg[r], bb[r], acc);
       }
     }
   }
