@@ -19,6 +19,7 @@
 // Both return d^2 = delta_bar^T x + x^T r from the final FP64 residual.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "device_common.hpp"
 #include "prof.hpp"
@@ -244,8 +245,17 @@ __global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__
         be = rz / cs->rho[t];
         cs->rho[t] = rz;
       }
+      vals[t] = cs->active[t] ? rr / (rtol2 * cs->bnorm2[t]) : 0.0;
+    } else {
+      vals[t] = 0.0;
     }
     cs->beta[t] = be;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double wmax = 0.0;
+    for (int c = 0; c < T; ++c) wmax = vals[c] > wmax ? vals[c] : wmax;
+    cs->worst = wmax;
   }
   recount_active(cs, T);
 }
@@ -507,11 +517,20 @@ static int stream_grid(long cap) {
 
 static size_t padded_cap(int n, int T) { return (((size_t)n * T + 15) / 16) * 16; }
 
-static nvd_status poll(Workspace* ws, hipStream_t s, int* n_active, int* n_oactive) {
-  NVD_HIP(hipMemcpyAsync(ws->h_pinned, &ws->cs->n_active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+struct PollWords {
+  int n_active, n_oactive, it_max, pad;
+  double worst;
+};
+
+static nvd_status poll(Workspace* ws, hipStream_t s, int* n_active, int* n_oactive,
+                       PollWords* all = nullptr) {
+  NVD_HIP(hipMemcpyAsync(ws->h_pinned, &ws->cs->n_active, sizeof(PollWords),
+                         hipMemcpyDeviceToHost, s));
   NVD_HIP(hipStreamSynchronize(s));
-  if (n_active) *n_active = ws->h_pinned[0];
-  if (n_oactive) *n_oactive = ws->h_pinned[1];
+  const PollWords* pw = reinterpret_cast<const PollWords*>(ws->h_pinned);
+  if (n_active) *n_active = pw->n_active;
+  if (n_oactive) *n_oactive = pw->n_oactive;
+  if (all) *all = *pw;
   return NVD_OK;
 }
 
@@ -537,26 +556,50 @@ static nvd_status cg_loop(DevGraph* g, Workspace* ws, int T, V* x, V* r, V* p, V
   const double sv = (double)sizeof(V);
   const double upd_bytes = (6.0 * T * sv + sv) * g->n;   // x, r, p, q in; x, r out; 1/deg
   const double dir_bytes = (3.0 * T * sv + sv) * g->n;   // r, p in; p out; 1/deg
+  // Iterations are enqueued in chunks; after each chunk the host reads four
+  // words (active count, largest iteration count, worst residual ratio) and
+  // sizes the next chunk from the observed decay of the worst residual, so
+  // that few launches run after the last column has converged.
   int done = 0;
-  int chunk = 8;
+  int chunk = 6;
+  int it0 = 0;                 // it_max at the start of the chunk
+  double prev_worst = -1.0;
+  int prev_it = 0;
+  std::vector<int> ids;
   while (done < max_iter) {
     const int todo = std::min(chunk, max_iter - done);
+    ids.clear();
     for (int it = 0; it < todo; ++it) {
       NVD_TRY(launch_spmm(sc, ws->red, s));
+      ids.push_back(prof_last_id());
       int pid = prof_begin(s, sizeof(V) == 8 ? PK_UPD64 : PK_UPD32, upd_bytes);
       NVD_TILE_SWITCH(T, (k_update<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, x, r, p, q, invd, rtol2,
                                                                 max_iter, ws->cs, ws->red)));
       prof_end(s, pid);
+      ids.push_back(pid);
       pid = prof_begin(s, sizeof(V) == 8 ? PK_DIR64 : PK_DIR32, dir_bytes);
       NVD_TILE_SWITCH(T, (k_direction<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, p, r, invd, ws->cs)));
       prof_end(s, pid);
+      ids.push_back(pid);
     }
     NVD_HIP(hipGetLastError());
     done += todo;
-    int na = 0;
-    NVD_TRY(poll(ws, s, &na, nullptr));
-    if (na == 0) break;
-    chunk = std::min(chunk * 2, 32);
+    PollWords pw{};
+    NVD_TRY(poll(ws, s, nullptr, nullptr, &pw));
+    // launches past the last active iteration returned at once: not timed work
+    const int ran = std::max(0, std::min(todo, pw.it_max - it0));
+    for (size_t k = (size_t)ran * 3; k < ids.size(); ++k) prof_mark_idle(ids[k]);
+    it0 = pw.it_max;
+    if (pw.n_active == 0) break;
+    int next = 8;
+    if (prev_worst > 0.0 && pw.worst > 0.0 && pw.worst < prev_worst && pw.it_max > prev_it) {
+      const double rate = std::log(pw.worst / prev_worst) / (double)(pw.it_max - prev_it);
+      const double need = std::log(1.0 / pw.worst) / rate;   // iterations to reach ratio 1
+      next = (int)std::ceil(need * 1.05) + 1;
+    }
+    prev_worst = pw.worst;
+    prev_it = pw.it_max;
+    chunk = std::max(1, std::min(next, 64));
   }
   return NVD_OK;
 }

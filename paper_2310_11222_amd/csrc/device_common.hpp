@@ -139,13 +139,15 @@ __device__ bool grid_reduce(double* vals, int ndt, const GridRed& red) {
 __device__ __forceinline__ void recount_active(ColState* cs, int T) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    int a = 0, o = 0;
+    int a = 0, o = 0, im = 0;
     for (int c = 0; c < T; ++c) {
       a += cs->active[c];
       o += cs->oactive[c];
+      im = cs->it_cur[c] > im ? cs->it_cur[c] : im;
     }
     cs->n_active = a;
     cs->n_oactive = o;
+    cs->it_max = im;
   }
 }
 

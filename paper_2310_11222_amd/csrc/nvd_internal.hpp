@@ -49,9 +49,11 @@ struct ColState {
   int it_cur[kMaxTile];     // iterations of the running CG
   int status[kMaxTile];
   int refine[kMaxTile];
-  int n_active;             // count of active[] (host polls this)
+  int n_active;             // count of active[] (host polls these four words)
   int n_oactive;
-  int pad[2];
+  int it_max;               // largest it_cur[] over the tile
+  int pad;
+  double worst;             // largest rr / (rtol^2 bnorm2) over active columns
 };
 
 // Two-level, fixed-order grid reduction scratch.

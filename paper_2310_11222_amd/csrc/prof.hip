@@ -14,10 +14,12 @@ struct Rec {
   hipEvent_t a = nullptr, b = nullptr;
   int kind = 0;
   double bytes = 0.0;
+  bool idle = false;
 };
 std::vector<Rec> g_recs;
 size_t g_used = 0;
 bool g_on = false;
+int g_last = -1;
 }  // namespace
 
 bool prof_enabled() { return g_on; }
@@ -32,8 +34,16 @@ int prof_begin(hipStream_t s, int kind, double bytes) {
   Rec& r = g_recs[g_used];
   r.kind = kind;
   r.bytes = bytes;
+  r.idle = false;
   if (hipEventRecord(r.a, s) != hipSuccess) return -1;
+  g_last = (int)g_used;
   return (int)g_used++;
+}
+
+int prof_last_id() { return g_on ? g_last : -1; }
+
+void prof_mark_idle(int id) {
+  if (id >= 0 && (size_t)id < g_used) g_recs[id].idle = true;
 }
 
 void prof_end(hipStream_t s, int id) {
@@ -64,6 +74,7 @@ nvd_status nvd_prof_read(double* ms, int64_t* launches, double* bytes) {
   }
   for (size_t i = 0; i < g_used; ++i) {
     Rec& r = g_recs[i];
+    if (r.idle) continue;
     NVD_HIP(hipEventSynchronize(r.b));
     float t = 0.0f;
     NVD_HIP(hipEventElapsedTime(&t, r.a, r.b));

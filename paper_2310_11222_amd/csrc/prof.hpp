@@ -10,4 +10,6 @@ enum ProfKind {
 bool prof_enabled();
 int prof_begin(hipStream_t s, int kind, double bytes);
 void prof_end(hipStream_t s, int id);
+int prof_last_id();            // id returned by the most recent prof_begin (-1 if none)
+void prof_mark_idle(int id);   // exclude a record (a launch that found no work)
 }  // namespace nvd
