@@ -182,6 +182,14 @@ nvd_status nvd_distances(nvd_graph* g, int32_t k, const double* P,
                          double* d_out, double* X_inout, int64_t ldx,
                          nvd_pair_info* info, void* stream);
 
+/* ---- tile autotuner --------------------------------------------------------
+ * The tile (pairs per SpMM pass) and the neighbour lanes per row that
+ * nvd_distances uses for k pairs when opts->tile_k == 0: candidates are
+ * timed on this graph on first use (device work on `stream`) and cached in
+ * the handle.  Environment variable NVD_TUNE=0 selects a fixed heuristic. */
+nvd_status nvd_tune_query(nvd_graph* g, int32_t k, int32_t precision,
+                          int32_t* tile, int32_t* nl, void* stream);
+
 /* ---- adjoint of d^2 with respect to the edge weights ---------------------
  * Given X (device float64 n x k, ldx; normally the X_inout of a previous
  * nvd_distances call) and gscale (device float64 [k], the upstream

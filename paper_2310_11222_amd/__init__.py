@@ -164,6 +164,14 @@ class Graph:
         infos = [{f: getattr(i, f) for f, _ in PairInfo._fields_} for i in info]
         return d, X, infos
 
+    def tuning(self, k, precision="mixed"):
+        """(tile, neighbour lanes) the autotuner picks for k pairs."""
+        t = C.c_int32()
+        nl = C.c_int32()
+        check(load().nvd_tune_query(self._h, k, {"fp64": NVD_FP64, "mixed": NVD_MIXED}[precision],
+                                    C.byref(t), C.byref(nl), _stream()), "nvd_tune_query")
+        return t.value, nl.value
+
     def grad_weights(self, X, gscale):
         """-1/2 sum_j g_j (x_i - x_c)^2 for every input CSR entry (i, c)."""
         torch = _torch()

@@ -48,10 +48,6 @@ __global__ __launch_bounds__(kBS) void k_grad_w(int n, const int* rp, const int*
 
 using namespace nvd;
 
-struct nvd_graph {
-  DevGraph* g;
-};
-
 struct nvd_batch;   // defined in batch.hip
 
 static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -246,6 +242,7 @@ nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double*
   for (int c0 = 0; c0 < k && st == NVD_OK;) {
     int T = tile;
     while (T > k - c0) T >>= 1;
+    sp.nl = tuned_nl(g, o.precision, T);
     st = ensure_workspace(g, T, o.precision == NVD_MIXED);
     if (st == NVD_OK)
       st = solve_tile(g, T, P + c0, Q + c0, ld, sp, d_out + c0, X ? X + c0 : nullptr, ldx,

@@ -112,6 +112,7 @@ struct DevGraph {
   int64_t bytes = 0;
   Workspace* ws = nullptr;
   int tuned_tile[2][8] = {};   // [precision][log2 k bucket] -> tile (0 = not tuned)
+  int tuned_nl[2][8] = {};     // [precision][log2 tile] -> neighbour lanes (0 = default)
 };
 
 struct Workspace {
@@ -192,7 +193,13 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
 nvd_status project_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
                         double* Dbar, int64_t ldd, double* norms, hipStream_t s);
 int choose_tile(DevGraph* g, int k, int precision, hipStream_t s);
+int tuned_nl(const DevGraph* g, int precision, int T);
 int default_nl(int T);
 int default_short_grid(int n, int T, int nl);
 
 }  // namespace nvd
+
+// The opaque handle behind nvd_graph*.
+struct nvd_graph {
+  nvd::DevGraph* g;
+};

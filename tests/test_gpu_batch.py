@@ -1,0 +1,123 @@
+"""GPU parity of the batched persistent solver (many uneven graphs in one
+launch) against the CPU oracle, and against the same pairs solved one graph
+at a time."""
+import numpy as np
+import pytest
+
+import oracle
+from nvdgen import barabasi_albert, ws_connected, workload, Graph, cycle_graph
+
+from gpu_helpers import say, dev_graph, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _mk_batch(seed, sizes, k_list, weighted=True):
+    rng = np.random.default_rng(seed)
+    graphs, Ps, Qs = [], [], []
+    for i, (n, k) in enumerate(zip(sizes, k_list)):
+        if i % 2 == 0:
+            g = ws_connected(n, 6, 0.1, np.random.SeedSequence([seed, i]))
+        else:
+            g = barabasi_albert(n, 4, rng)
+        if weighted:
+            g = g.with_weights(rng.uniform(0.5, 2.0, g.num_edges))
+        P = np.where(rng.random((g.n, k)) < 0.2, rng.standard_normal((g.n, k)), 0.0)
+        Q = np.where(rng.random((g.n, k)) < 0.2, rng.standard_normal((g.n, k)), 0.0)
+        graphs.append(g)
+        Ps.append(P)
+        Qs.append(Q)
+    return graphs, Ps, Qs
+
+
+def _oracle(g, P, Q):
+    if g.n <= 4000:
+        return oracle.ge_dense(g.n, g.row_ptr, g.col_idx, g.w, P, Q)["d"]
+    return oracle.ge_pcg(g.n, g.row_ptr, g.col_idx, g.w, P, Q)["d"]
+
+
+def _run(graphs, Ps, Qs, precision, **kw):
+    import paper_2310_11222_amd as nvd
+    dgs = [dev_graph(g) for g in graphs]
+    batch = nvd.Batch(dgs)
+    d, X, info = batch.distances(Ps, Qs, precision=precision, **kw)
+    return d.cpu().numpy(), X, info, dgs
+
+
+@pytest.mark.parametrize("precision,tol", [("mixed", 1e-6), ("fp64", 1e-8)])
+def test_small_batch_matches_oracle(precision, tol):
+    sizes = [300, 1200, 3500, 800, 2000, 450, 3000, 900, 1500, 600]
+    ks = [8] * len(sizes)
+    graphs, Ps, Qs = _mk_batch(1, sizes, ks)
+    say("batch small", precision)
+    d, X, info, _ = _run(graphs, Ps, Qs, precision, rtol=1e-10 if precision == "fp64" else 1e-8,
+                         return_x=True)
+    off = 0
+    xoff = 0
+    for g, P, Q in zip(graphs, Ps, Qs):
+        ref = _oracle(g, P, Q)
+        e = rel_err(d[off:off + P.shape[1]], ref)
+        assert e.max() <= tol, (g.n, e)
+        xr = oracle.ge_dense(g.n, g.row_ptr, g.col_idx, g.w, P, Q)["x"]
+        xg = X[xoff:xoff + g.n * P.shape[1]].cpu().numpy().reshape(g.n, -1)
+        np.testing.assert_allclose(xg, xr, rtol=1e-4, atol=1e-6 * np.abs(xr).max())
+        off += P.shape[1]
+        xoff += g.n * P.shape[1]
+    assert all(i["status"] == 0 for i in info)
+
+
+def test_uneven_k_and_equivalence_with_single_solves():
+    sizes = [700, 1600, 400, 2500, 1000]
+    ks = [1, 8, 3, 5, 2]
+    graphs, Ps, Qs = _mk_batch(2, sizes, ks)
+    say("batch uneven k")
+    d, _, info, dgs = _run(graphs, Ps, Qs, "mixed", rtol=1e-8)
+    off = 0
+    for dg, g, P, Q in zip(dgs, graphs, Ps, Qs):
+        single, _, _ = dg.distances(P, Q, precision="mixed", rtol=1e-8)
+        single = single.cpu().numpy()
+        ref = _oracle(g, P, Q)
+        assert rel_err(d[off:off + P.shape[1]], single).max() <= 2e-6
+        assert rel_err(d[off:off + P.shape[1]], ref).max() <= 1e-6
+        off += P.shape[1]
+
+
+@pytest.mark.parametrize("precision,tol", [("mixed", 1e-6), ("fp64", 1e-8)])
+def test_team_path_large_graph_among_small(precision, tol):
+    """One graph far above a block's share of the work gets a multi-block
+    team (barriers, coherent shared vectors); the rest go to the pool."""
+    sizes = [60000] + [400] * 30
+    ks = [8] * len(sizes)
+    graphs, Ps, Qs = _mk_batch(3, sizes, ks)
+    say("batch team", precision)
+    d, _, info, _ = _run(graphs, Ps, Qs, precision, rtol=1e-10 if precision == "fp64" else 1e-8)
+    ref0 = oracle.ge_pcg(graphs[0].n, graphs[0].row_ptr, graphs[0].col_idx, graphs[0].w,
+                         Ps[0], Qs[0])["d"]
+    assert rel_err(d[:8], ref0).max() <= tol
+    off = 8
+    for g, P, Q in zip(graphs[1:], Ps[1:], Qs[1:]):
+        assert rel_err(d[off:off + 8], _oracle(g, P, Q)).max() <= tol
+        off += 8
+
+
+def test_workload_shape_reduced_scale():
+    """The 512-graph workload's recipe at 1/10 of the node counts, 64 graphs."""
+    w = workload(3, scale=0.1, num_graphs=64)
+    say("batch c3 reduced", sum(g.n for g in w.graphs))
+    d, _, info, _ = _run(w.graphs, w.P, w.Q, "mixed", rtol=1e-8)
+    off = 0
+    worst = 0.0
+    for g, P, Q in zip(w.graphs, w.P, w.Q):
+        worst = max(worst, rel_err(d[off:off + 8], _oracle(g, P, Q)).max())
+        off += 8
+    assert worst <= 1e-6, worst
+
+
+def test_batch_rejects_disconnected_graph():
+    import paper_2310_11222_amd as nvd
+    g1 = barabasi_albert(200, 2, np.random.default_rng(4))
+    g2 = Graph(10, np.array([0, 5]), np.array([1, 6]))
+    say("batch reject")
+    with pytest.raises(nvd.NvdError) as ei:
+        nvd.Batch([dev_graph(g1), dev_graph(g2)])
+    assert ei.value.status == 8
