@@ -190,6 +190,17 @@ nvd_status nvd_distances(nvd_graph* g, int32_t k, const double* P,
 nvd_status nvd_tune_query(nvd_graph* g, int32_t k, int32_t precision,
                           int32_t* tile, int32_t* nl, void* stream);
 
+/* ---- new edge weights for an existing graph -------------------------------
+ * w: device float64 [nnz] in the order of the CSR given to nvd_graph_create
+ * (self-loop entries ignored).  Replaces the weights (a graph created with
+ * unit weights becomes weighted), recomputes degrees and their inverses, and
+ * checks on the device that every value is finite and positive and equal to
+ * its mirror entry's (NVD_E_GRAPH otherwise; the graph then holds the
+ * rejected values and must not be used until valid weights are set).
+ * Synchronous with respect to `stream`.  Batches made earlier keep their
+ * own copy. */
+nvd_status nvd_graph_set_weights(nvd_graph* g, const double* w, void* stream);
+
 /* ---- adjoint of d^2 with respect to the edge weights ---------------------
  * Given X (device float64 n x k, ldx; normally the X_inout of a previous
  * nvd_distances call) and gscale (device float64 [k], the upstream

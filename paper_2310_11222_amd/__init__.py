@@ -172,6 +172,14 @@ class Graph:
                                     C.byref(t), C.byref(nl), _stream()), "nvd_tune_query")
         return t.value, nl.value
 
+    def set_weights(self, w):
+        """Replace the edge weights (device float64, input CSR order)."""
+        torch = _torch()
+        w = w.detach().to(device="cuda", dtype=torch.float64).contiguous()
+        assert w.numel() == self.nnz_in
+        check(load().nvd_graph_set_weights(self._h, _ptr(w), _stream()), "nvd_graph_set_weights")
+        self.weighted = True
+
     def grad_weights(self, X, gscale):
         """-1/2 sum_j g_j (x_i - x_c)^2 for every input CSR entry (i, c)."""
         torch = _torch()
@@ -248,3 +256,6 @@ def distance(g: Graph, p, q, **kw):
     """d(p, q) for vectors or column blocks; returns (d, info)."""
     d, _, info = g.distances(p, q, **kw)
     return d, info
+
+
+from .autograd import DistanceSq, distance_sq, distance_t  # noqa: E402,F401

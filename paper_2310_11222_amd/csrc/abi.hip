@@ -44,6 +44,44 @@ __global__ __launch_bounds__(kBS) void k_grad_w(int n, const int* rp, const int*
   }
 }
 
+// New edge weights from a device array in the input CSR order: every
+// internal entry takes its value, and the value is checked (finite, > 0,
+// equal to the mirror entry's).  flag bit 1: bad value, bit 2: asymmetric.
+__global__ void k_set_weights(int n, const int* rp, const int* ci, const int* in_pos,
+                              const double* w_in, double* w64, float* w32, int* flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const double v = w_in[in_pos ? in_pos[e] : e];
+    if (!(v > 0.0) || !isfinite(v)) atomicOr(flag, 1);
+    w64[e] = v;
+    w32[e] = (float)v;
+    const int j = ci[e];
+    int lo = rp[j], hi = rp[j + 1];
+    while (lo < hi) {                  // mirror entry (j, i)
+      const int mid = (lo + hi) >> 1;
+      if (ci[mid] < i)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (lo >= rp[j + 1] || ci[lo] != i || w_in[in_pos ? in_pos[lo] : lo] != v) atomicOr(flag, 2);
+  }
+}
+
+__global__ void k_degree_refresh(int n, const int* rp, const double* w64, double* deg64,
+                                 float* deg32, double* invd64, float* invd32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double d = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) d += w64[e];
+  deg64[i] = d;
+  deg32[i] = (float)d;
+  const double inv = d > 0.0 ? 1.0 / d : 0.0;
+  invd64[i] = inv;
+  invd32[i] = (float)inv;
+}
+
 }  // namespace nvd
 
 using namespace nvd;
@@ -266,6 +304,48 @@ nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double*
   if (info) std::copy(hinfo.begin(), hinfo.end(), info);
   if (agg != NVD_OK) set_error("nvd_distances: some pairs did not converge (see info)");
   return agg;
+}
+
+nvd_status nvd_graph_set_weights(nvd_graph* h, const double* w, void* stream) {
+  set_error("");
+  if (!h || !w) {
+    set_error("nvd_graph_set_weights: NULL argument");
+    return NVD_E_ARG;
+  }
+  DevGraph* g = h->g;
+  hipStream_t s = as_stream(stream);
+  if (!g->w64) {
+    NVD_HIP(hipMalloc((void**)&g->w64, sizeof(double) * std::max(g->nnz, 1)));
+    NVD_HIP(hipMalloc((void**)&g->w32, sizeof(float) * std::max(g->nnz, 1)));
+    g->bytes += (int64_t)12 * std::max(g->nnz, 1);
+  }
+  int* flag = nullptr;
+  NVD_HIP(hipMalloc((void**)&flag, sizeof(int)));
+  int hflag = 0;
+  hipError_t e = hipMemcpyAsync(flag, &hflag, sizeof(int), hipMemcpyHostToDevice, s);
+  const int grid = (g->n + 255) / 256;
+  if (e == hipSuccess) {
+    k_set_weights<<<grid, 256, 0, s>>>(g->n, g->rp, g->ci, g->in_pos, w, g->w64, g->w32, flag);
+    k_degree_refresh<<<grid, 256, 0, s>>>(g->n, g->rp, g->w64, g->deg64, g->deg32, g->invd64,
+                                          g->invd32);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(flag);
+  if (e != hipSuccess) {
+    set_error(std::string("nvd_graph_set_weights: ") + hipGetErrorString(e));
+    return NVD_E_DEVICE;
+  }
+  g->weighted = true;
+  if (hflag) {
+    set_error(std::string("nvd_graph_set_weights: ") +
+              ((hflag & 1) ? "a weight is not a finite positive number" : "") +
+              ((hflag & 3) == 3 ? "; " : "") +
+              ((hflag & 2) ? "weights of an entry and its mirror differ" : ""));
+    return NVD_E_GRAPH;
+  }
+  return NVD_OK;
 }
 
 nvd_status nvd_grad_weights(nvd_graph* h, int32_t k, const double* X, int64_t ldx,
