@@ -226,10 +226,19 @@ nvd_status nvd_grad_weights(nvd_graph* g, int32_t k, const double* X,
  *   sum_{h<g} n_h k_h.
  * d_out: device float64 [sum k_g] (graph-major).  X_out: NULL or device
  *   float64 packed like P.  info: NULL or host [sum k_g].
- * Synchronous with respect to `stream`. */
+ * Graphs must be connected (NVD_E_UNSUPPORTED at create time otherwise).
+ * The launch is captured in a hipGraph and replayed by later calls with the
+ * same pointers, pair counts and options (NVD_BATCH_GRAPH=0 launches
+ * directly).  Synchronous with respect to `stream`. */
 nvd_status nvd_batch_create(int32_t G, nvd_graph* const* graphs, void* stream,
                             nvd_batch** out);
 nvd_status nvd_batch_destroy(nvd_batch* b);
+/* Counts of how batched calls ran: launches captured into a hipGraph,
+ * replays of a captured graph (calls whose arguments matched the previous
+ * capture), and direct launches (capture off via NVD_BATCH_GRAPH=0, or
+ * refused by the runtime). */
+nvd_status nvd_batch_query(const nvd_batch* b, int64_t* captures,
+                           int64_t* replays, int64_t* eager);
 nvd_status nvd_batch_distances(nvd_batch* b, const int32_t* k_per_graph,
                                const double* P, const double* Q,
                                const nvd_opts* opts, double* d_out,

@@ -215,14 +215,31 @@ class Batch:
         except Exception:
             pass
 
-    def distances(self, P_list, Q_list, precision="mixed", rtol=1e-8, inner_rtol=1e-5,
-                  max_iter=20000, max_refine=30, return_x=False):
+    def query(self) -> dict:
+        c, r, e = C.c_int64(), C.c_int64(), C.c_int64()
+        check(load().nvd_batch_query(self._h, C.byref(c), C.byref(r), C.byref(e)), "nvd_batch_query")
+        return {"captures": c.value, "replays": r.value, "eager": e.value}
+
+    @staticmethod
+    def pack(P_list, Q_list):
+        """Graph-major packed device copies of per-graph (n_g, k_g) blocks."""
         torch = _torch()
         ks = np.array([p.shape[1] if p.ndim == 2 else 1 for p in P_list], dtype=np.int32)
         Pf = torch.cat([_as_dev64(p, "P").reshape(-1) for p in P_list])
         Qf = torch.cat([_as_dev64(q, "Q").reshape(-1) for q in Q_list])
+        return ks, Pf, Qf
+
+    def distances(self, P_list, Q_list, precision="mixed", rtol=1e-8, inner_rtol=1e-5,
+                  max_iter=20000, max_refine=30, return_x=False, packed=None, out=None):
+        """packed = (ks, Pf, Qf) from Batch.pack reuses device buffers (and so
+        the captured launch); out = preallocated d tensor."""
+        torch = _torch()
+        if packed is None:
+            ks, Pf, Qf = self.pack(P_list, Q_list)
+        else:
+            ks, Pf, Qf = packed
         K = int(ks.sum())
-        d = torch.empty(K, dtype=torch.float64, device="cuda")
+        d = out if out is not None else torch.empty(K, dtype=torch.float64, device="cuda")
         X = torch.empty_like(Pf) if return_x else None
         info = (PairInfo * K)()
         o = opts(precision, rtol, inner_rtol, max_iter, max_refine)

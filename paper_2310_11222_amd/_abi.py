@@ -58,6 +58,7 @@ SIGNATURES = {
     "nvd_batch_create": (_I32, [_I32, _P, _P, C.POINTER(_P)]),
     "nvd_batch_destroy": (_I32, [_P]),
     "nvd_batch_distances": (_I32, [_P, _P, _P, _P, C.POINTER(NvdOpts), _P, _P, _P, _P]),
+    "nvd_batch_query": (_I32, [_P, _P, _P, _P]),
     "nvd_tune_query": (_I32, [_P, _I32, _I32, _P, _P, _P]),
     "nvd_prof_enable": (_I32, [_I32]),
     "nvd_prof_read": (_I32, [_P, _P, _P]),

@@ -24,6 +24,7 @@
 // d^2 = delta_bar^T x + x^T (delta_bar - L x) in FP64.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <numeric>
 #include <vector>
 
@@ -630,9 +631,29 @@ struct nvd_batch {
   nvd_pair_info* info = nullptr;
   int info_cap = 0;
   int64_t bytes = 0;
+  // captured launch (reset + persistent kernel), replayed while the call's
+  // arguments are unchanged
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<long> key;
+  bool capture_failed = false;
+  int64_t replays = 0;
+  int64_t captures = 0;
+  int64_t eager = 0;
 };
 
+static void batch_drop_graph(nvd_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->key.clear();
+}
+
 static void batch_free(nvd_batch* b) {
+  batch_drop_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   void* ptrs[] = {b->rp, b->ci, b->w64, b->w32, b->deg64, b->deg32, b->invd64, b->invd32,
                   b->long_rows, b->b64, b->x64, b->r64, b->cv, b->rv, b->pv, b->qv, b->gd,
                   b->plan_buf, b->ctr, b->pool_next, b->err, b->part, b->info};
@@ -886,6 +907,11 @@ static nvd_status run_batch(nvd_batch* b, const std::vector<int>& ks, const doub
     b->info_cap = K;
   }
   BatchPlan pl = make_plan(b, ks, T, B);
+  std::vector<long> key = {T, (long)sizeof(V), (long)(intptr_t)P, (long)(intptr_t)Q,
+                           (long)(intptr_t)d_out, (long)(intptr_t)X, B, o.max_iter, o.max_refine,
+                           (long)std::llround(std::log10(o.rtol) * 1e6),
+                           (long)std::llround(std::log10(o.inner_rtol) * 1e6)};
+  key.insert(key.end(), ks.begin(), ks.end());
   const size_t plan_ints = (size_t)B + 3 * pl.nteams + pl.pool.size() + pl.nteams;
   if ((size_t)b->plan_cap < plan_ints) {
     if (b->plan_buf) (void)hipFree(b->plan_buf);
@@ -944,9 +970,54 @@ static nvd_status run_batch(nvd_batch* b, const std::vector<int>& ks, const doub
   a.max_iter = o.max_iter;
   a.max_refine = mixed ? o.max_refine : std::max(2, std::min(o.max_refine, 3));
   a.err = b->err;
-  k_batch_reset<<<(pl.nteams + 255) / 256, 256, 0, s>>>(a.team_ctr, pl.nteams, b->pool_next, b->err);
-  NVD_HIP(hipGetLastError());
-  NVD_TRY((launch_batch<T, V>(b, a, s)));
+  // the launch sequence: counters reset by a kernel (no memset node), then
+  // the persistent kernel
+  auto enqueue = [&](hipStream_t q) -> nvd_status {
+    k_batch_reset<<<(pl.nteams + 255) / 256, 256, 0, q>>>(a.team_ctr, pl.nteams, b->pool_next,
+                                                          b->err);
+    NVD_HIP(hipGetLastError());
+    return launch_batch<T, V>(b, a, q);
+  };
+  const char* ge = std::getenv("NVD_BATCH_GRAPH");
+  const bool use_graph = !(ge && ge[0] == '0') && !b->capture_failed;
+  bool done = false;
+  if (use_graph) {
+    if (b->gexec && b->key == key) {
+      NVD_HIP(hipGraphLaunch(b->gexec, s));
+      ++b->replays;
+      done = true;
+    } else {
+      batch_drop_graph(b);
+      if (!b->cap_stream) NVD_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+      // the device plan was copied on s: make the capture stream wait for it
+      NVD_HIP(hipStreamSynchronize(s));
+      hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed);
+      nvd_status st = e == hipSuccess ? enqueue(b->cap_stream) : NVD_E_DEVICE;
+      hipGraph_t gr = nullptr;
+      hipError_t e2 = hipStreamEndCapture(b->cap_stream, &gr);
+      if (st == NVD_OK && e == hipSuccess && e2 == hipSuccess && gr) {
+        if (hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0) == hipSuccess) {
+          b->graph = gr;
+          b->key = key;
+          ++b->captures;
+          NVD_HIP(hipGraphLaunch(b->gexec, s));
+          done = true;
+        } else {
+          (void)hipGraphDestroy(gr);
+        }
+      } else if (gr) {
+        (void)hipGraphDestroy(gr);
+      }
+      if (!done) {
+        b->capture_failed = true;     // fall back to direct launches from now on
+        (void)hipGetLastError();
+      }
+    }
+  }
+  if (!done) {
+    NVD_TRY(enqueue(s));
+    ++b->eager;
+  }
   NVD_HIP(hipMemcpyAsync(b->h_err, b->err, sizeof(int), hipMemcpyDeviceToHost, s));
   if (info_host)
     NVD_HIP(hipMemcpyAsync(info_host, b->info, sizeof(nvd_pair_info) * K, hipMemcpyDeviceToHost, s));
@@ -959,6 +1030,18 @@ static nvd_status run_batch(nvd_batch* b, const std::vector<int>& ks, const doub
 }
 
 }  // namespace nvd
+
+extern "C" nvd_status nvd_batch_query(const nvd_batch* b, int64_t* captures, int64_t* replays,
+                                      int64_t* eager) {
+  if (!b || !captures || !replays || !eager) {
+    set_error("nvd_batch_query: NULL argument");
+    return NVD_E_ARG;
+  }
+  *captures = b->captures;
+  *replays = b->replays;
+  *eager = b->eager;
+  return NVD_OK;
+}
 
 extern "C" nvd_status nvd_batch_distances(nvd_batch* b, const int32_t* k_per_graph,
                                           const double* P, const double* Q,

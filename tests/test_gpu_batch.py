@@ -121,3 +121,37 @@ def test_batch_rejects_disconnected_graph():
     with pytest.raises(nvd.NvdError) as ei:
         nvd.Batch([dev_graph(g1), dev_graph(g2)])
     assert ei.value.status == 8
+
+
+def test_graph_capture_replays_match_eager():
+    """The batched launch is captured once and replayed; every replay (with
+    the program's own eager GPU work and synchronisations in between) must
+    reproduce the direct-launch result bit for bit."""
+    import os
+    import torch
+    import paper_2310_11222_amd as nvd
+    sizes = [900, 2500, 400, 1800, 60000]
+    ks = [8, 8, 4, 8, 8]
+    graphs, Ps, Qs = _mk_batch(6, sizes, ks)
+    say("batch graph replay")
+    dgs = [dev_graph(g) for g in graphs]
+    batch = nvd.Batch(dgs)
+    packed = batch.pack(Ps, Qs)
+    K = int(sum(ks))
+    os.environ["NVD_BATCH_GRAPH"] = "0"
+    try:
+        eager = batch.distances(None, None, packed=packed)[0].cpu().numpy()
+    finally:
+        del os.environ["NVD_BATCH_GRAPH"]
+    out = torch.empty(K, dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        out.fill_(-1.0)
+        d = batch.distances(None, None, packed=packed, out=out)[0].cpu().numpy()
+        assert np.array_equal(d, eager), (rep, np.abs(d - eager).max())
+        # unrelated eager work between replays
+        dgs[1].distances(Ps[1], Qs[1], precision="fp64")
+        torch.cuda.synchronize()
+    q = batch.query()
+    print("[batch-graph]", q, flush=True)
+    assert q["eager"] >= 1
+    assert q["captures"] == 1 and q["replays"] == 3, q
