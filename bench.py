@@ -38,6 +38,71 @@ def load_golden():
     return np.array([float(v) for v in g["d"]])
 
 
+def load_golden_batch():
+    p = os.path.join(ROOT, "tests", "golden", "c3_expected.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        g = json.load(f)
+    import numpy as np
+    return np.array([float(v) for v in g["d"]])
+
+
+def bench_batched(steps, warmup):
+    """512 connected graphs of uneven size (n log-uniform in [1e3, 1e5], half
+    Watts-Strogatz k=6 beta=0.1, half Barabasi-Albert m=4, weights
+    uniform[0.5, 2)), 8 pairs each: one persistent launch (captured in a
+    hipGraph) for all 4096 distances, FP32 CG + FP64 refinement to 1e-8;
+    beside it the plain FP64 solver called one graph at a time."""
+    import numpy as np
+    import torch
+    import paper_2310_11222_amd as nvd
+    from nvdgen import workload
+    t0 = time.perf_counter()
+    w = workload(3)
+    log(f"batched workload: {len(w.graphs)} graphs, n_total={sum(g.n for g in w.graphs)}, "
+        f"gen {time.perf_counter() - t0:.1f}s")
+    dgs = [nvd.Graph(g.row_ptr, g.col_idx, g.w) for g in w.graphs]
+    batch = nvd.Batch(dgs)
+    packed = batch.pack(w.P, w.Q)
+    K = int(packed[0].sum())
+    out = torch.empty(K, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        batch.distances(None, None, packed=packed, out=out, rtol=w.rtol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        d, _, info = batch.distances(None, None, packed=packed, out=out, rtol=w.rtol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d = d.cpu().numpy()
+    value = K * steps / (t1 - t0)
+    # plain FP64 solver, one graph at a time, same GPU
+    t2 = time.perf_counter()
+    d64 = []
+    for dg, P, Q in zip(dgs, w.P, w.Q):
+        dd, _, _ = dg.distances(P, Q, precision="fp64", rtol=w.rtol)
+        d64.append(dd)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    d64 = torch.cat(d64).cpu().numpy()
+    gold = load_golden_batch()
+    res = {"workload": "batch512_ws_k6_ba_m4_k8", "value": round(value, 1), "unit": "distances/s",
+           "ms_per_step": round((t1 - t0) * 1e3 / steps, 3), "pairs": K,
+           "graph_launch": batch.query(),
+           "iters_mean": float(np.mean([i["iters"] for i in info])),
+           "fp64_one_graph_at_a_time": {"value": round(K / (t3 - t2), 1), "unit": "distances/s"},
+           "max_rel_err": None, "max_rel_err_fp64": None}
+    if gold is not None and gold.size == K:
+        res["max_rel_err"] = float(np.max(np.abs(d - gold) / gold))
+        res["max_rel_err_fp64"] = float(np.max(np.abs(d64 - gold) / gold))
+    log(f"batched: {res}")
+    batch.close()
+    for dg in dgs:
+        dg.close()
+    return res
+
+
 def cpu_baseline(w, pairs):
     """The oracle (FP64 Jacobi-PCG route, unmodified defaults) on `pairs`
     pairs of the same workload, single-threaded."""
@@ -60,10 +125,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
-    ap.add_argument("--cpu-pairs", type=int, default=2)
+    ap.add_argument("--cpu-pairs", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--inner-rtol", type=float, default=1e-5)
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -166,6 +232,12 @@ def main():
                          f"(true rel. residual 1e-13), {secs:.1f} s single-threaded"}
         log(f"cpu oracle {rate:.3f} distances/s ({secs:.1f}s)")
 
+    batched = None
+    if not args.no_batched:
+        dg.close()
+        torch.cuda.empty_cache()
+        batched = bench_batched(max(2, args.steps // 2), 1)
+
     out = {
         "metric": "NVD distances/sec at rel err <=1e-6 vs FP64 oracle; SpMV HBM GB/s % of peak",
         "value": round(value, 2),
@@ -187,6 +259,7 @@ def main():
         "fp64_path": {"value": round(value64, 2), "unit": "distances/s",
                       "ms_per_step": round(t64 * 1e3, 3)},
         "accuracy": acc,
+        "batched": batched,
         "iters_mean": float(np.mean(iters_mixed)),
         "refine_mean": float(np.mean(refine)),
         "setup_s": round(setup_s, 3),

@@ -161,20 +161,70 @@ __device__ __forceinline__ void reduce_cols(Team& tm, double (&acc)[ND][1], int 
   team_reduce(tm, vals, ND * T);
 }
 
+// Column sums of ND dots when thread t holds N consecutive columns
+// (t*N + v) % T, T a multiple of N: lanes holding the same columns are
+// combined by shuffles, then the 8 waves' sums in wave order (fixed order).
+// Needs 8*ND*T doubles of sh; result in vals[d*T + c].
+template <int ND, int N>
+__device__ __forceinline__ void block_reduce_vec(double (&acc)[ND][N], int T, double* sh,
+                                                 double* vals) {
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int L = T / N;            // lanes with distinct column sets
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int v = 0; v < N; ++v) {
+      double x = acc[d][v];
+      for (int off = L; off < 64; off <<= 1) x += __shfl_xor(x, off, 64);
+      acc[d][v] = x;
+    }
+  if (lane < L) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+#pragma unroll
+      for (int v = 0; v < N; ++v) sh[(wave * ND + d) * T + lane * N + v] = acc[d][v];
+  }
+  __syncthreads();
+  if (t < T) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      double s = 0.0;
+      for (int w = 0; w < BBS / 64; ++w) s += sh[(w * ND + d) * T + t];
+      vals[d * T + t] = s;
+    }
+  }
+  __syncthreads();
+}
+
 template <int T>
 struct BLanes {
   static constexpr int NL = T >= 16 ? 1 : (T == 8 ? 2 : (T == 4 ? 4 : 8));
   static constexpr int G = T * NL;
+  static constexpr int R = 4;                 // rows carried at once per lane group
+};
+
+// Working storage of one block (kernel-level LDS, shared by both code paths).
+struct Lds {
+  double* sh;        // [4*BBS]
+  double* sh_long;   // [BBS]
+  double* vals;      // [4*kMaxTile]
+  double *rho, *alpha, *beta, *bn2, *obn2, *mean;   // [kMaxTile] each
+  int *act, *oact, *it, *itc, *ref, *stat;          // [kMaxTile] each
+  int* cnt;          // [2]: active, open
 };
 
 // Laplacian apply on rows [lo, hi) of one graph.
 //   EPI_CG:    y = L x (V), acc[0] += x.y          (x = p, y = q)
 //   EPI_RESID: y = b - L x (double), acc = {sum y, y.y, b.x, x.y}
+// Short rows: groups of G = T*NL lanes, R rows per group at once, neighbour
+// indices loaded G at a time and shuffled out so gathers issue back to back.
 template <typename V, int T, bool SH, int EPI, int ND>
 __device__ void block_spmm(const BatchArgs& a, const BGraph& gd, int lo, int hi, const V* x,
                            V* y, const double* b, double (&acc)[ND][1], double* sh_long) {
   constexpr int NL = BLanes<T>::NL;
   constexpr int G = BLanes<T>::G;
+  constexpr int R = BLanes<T>::R;
   constexpr int RW = 64 / G;
   constexpr int MM = G / NL;
   constexpr int MB = MM < 8 ? MM : 8;
@@ -197,55 +247,94 @@ __device__ void block_spmm(const BatchArgs& a, const BGraph& gd, int lo, int hi,
     wv = reinterpret_cast<const V*>(a.w32 + gd.nnz_off);
     dgv = reinterpret_cast<const V*>(a.deg32 + gd.v_off / T);
   }
-  constexpr int ROWS_PER_STEP = (BBS / 64) * RW;
+  constexpr int ROWS_PER_WAVE = RW * R;
+  constexpr int ROWS_PER_STEP = (BBS / 64) * ROWS_PER_WAVE;
   for (int base = lo; base < hi; base += ROWS_PER_STEP) {
-    const int row = base + wave * RW + g;
-    if (row >= hi) continue;
-    const int rs = rp[row];
-    const int deg = rp[row + 1] - rs;
-    if (deg > kLongRow) continue;
-    const V own = vld<SH>(&x[(long)row * T + c]);
-    const V dg = unit ? (V)deg : dgv[row];
-    double bb = 0.0;
-    if constexpr (EPI == EPI_RESID) bb = b[(long)row * T + c];
-    V sum = (V)0;
-    for (int off = 0; off < deg; off += G) {
-      const int cnt = min(G, deg - off);
-      const int myc = li < cnt ? ci[rs + off + li] : 0;
-      const V myw = unit ? (V)1 : (li < cnt ? wv[rs + off + li] : (V)0);
+    int row[R], rs[R], deg[R];
+    bool mine[R];
+    V own[R], dg[R];
+    double bb[R];
+    int maxdeg = 0;
 #pragma unroll
-      for (int m0 = 0; m0 < MM; m0 += MB) {
-        if (NL * m0 >= cnt) break;
-        V xv[MB], ww[MB];
-#pragma unroll
-        for (int m = 0; m < MB; ++m) {
-          const int idx = j + NL * (m0 + m);
-          const int col = __shfl(myc, idx, G);
-          ww[m] = __shfl(myw, idx, G);
-          xv[m] = idx < cnt ? vld<SH>(&x[(long)col * T + c]) : (V)0;
-        }
-#pragma unroll
-        for (int m = 0; m < MB; ++m) sum += ww[m] * xv[m];
+    for (int r = 0; r < R; ++r) {
+      row[r] = base + wave * ROWS_PER_WAVE + r * RW + g;
+      rs[r] = 0;
+      deg[r] = -1;
+      if (row[r] < hi) {
+        rs[r] = rp[row[r]];
+        deg[r] = rp[row[r] + 1] - rs[r];
       }
     }
 #pragma unroll
-    for (int off = T; off < G; off <<= 1) sum += __shfl_xor(sum, off, 64);
+    for (int r = 0; r < R; ++r) {
+      mine[r] = deg[r] >= 0 && deg[r] <= kLongRow;
+      own[r] = mine[r] ? vld<SH>(&x[(long)row[r] * T + c]) : (V)0;
+      dg[r] = mine[r] ? (unit ? (V)deg[r] : dgv[row[r]]) : (V)0;
+      bb[r] = 0.0;
+      if constexpr (EPI == EPI_RESID) bb[r] = mine[r] ? b[(long)row[r] * T + c] : 0.0;
+      if (!mine[r]) deg[r] = 0;
+      maxdeg = deg[r] > maxdeg ? deg[r] : maxdeg;
+    }
+    V sum[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) sum[r] = (V)0;
+    for (int off = 0; off < maxdeg; off += G) {
+      int myc[R], cnt[R];
+      V myw[R];
+      int maxcnt = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        cnt[r] = deg[r] - off;
+        cnt[r] = cnt[r] < 0 ? 0 : (cnt[r] > G ? G : cnt[r]);
+        myc[r] = li < cnt[r] ? ci[rs[r] + off + li] : 0;
+        myw[r] = unit ? (V)1 : (li < cnt[r] ? wv[rs[r] + off + li] : (V)0);
+        maxcnt = cnt[r] > maxcnt ? cnt[r] : maxcnt;
+      }
+#pragma unroll
+      for (int m0 = 0; m0 < MM; m0 += MB) {
+        if (NL * m0 >= maxcnt) break;
+        V xv[R][MB], ww[R][MB];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+          for (int m = 0; m < MB; ++m) {
+            const int idx = j + NL * (m0 + m);
+            const int col = __shfl(myc[r], idx, G);
+            ww[r][m] = __shfl(myw[r], idx, G);
+            xv[r][m] = idx < cnt[r] ? vld<SH>(&x[(long)col * T + c]) : (V)0;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int m = 0; m < MB; ++m) sum[r] += ww[r][m] * xv[r][m];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int off = T; off < G; off <<= 1) sum[r] += __shfl_xor(sum[r], off, 64);
+    }
     if (j == 0) {
-      const V yv = dg * own - sum;
-      if constexpr (EPI == EPI_CG) {
-        y[(long)row * T + c] = yv;
-        acc[0][0] += (double)own * (double)yv;
-      } else {
-        const double rr = bb - (double)yv;
-        y[(long)row * T + c] = (V)rr;
-        acc[0][0] += rr;
-        acc[1][0] += rr * rr;
-        acc[2][0] += bb * (double)own;
-        acc[3][0] += (double)own * rr;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (!mine[r]) continue;
+        const V yv = dg[r] * own[r] - sum[r];
+        if constexpr (EPI == EPI_CG) {
+          y[(long)row[r] * T + c] = yv;
+          acc[0][0] += (double)own[r] * (double)yv;
+        } else {
+          const double rr = bb[r] - (double)yv;
+          y[(long)row[r] * T + c] = (V)rr;
+          acc[0][0] += rr;
+          acc[1][0] += rr * rr;
+          acc[2][0] += bb[r] * (double)own[r];
+          acc[3][0] += (double)own[r] * rr;
+        }
       }
     }
   }
-  // rows with many neighbours: the whole block, 512/T lanes per column
+  // rows with many neighbours: the whole block, BBS/T lanes per column
   const int* lr = a.long_rows + gd.long_off;
   constexpr int NJ = BBS / T;
   for (int q = 0; q < gd.n_long; ++q) {
@@ -295,14 +384,17 @@ __device__ __forceinline__ int split_row(const int* rp, int n, int rank, int S) 
   return lo;
 }
 
+// Streaming loop over the block's elements e in [e0, e1) (row-major, T
+// columns).  Single-block graphs use 16-byte vectors when T is a multiple of
+// the vector width; shared (team) vectors use coherent scalar accesses.
+template <typename V, int T, bool SH>
+struct Stream {
+  static constexpr int N = Vec16<V>::N;
+  static constexpr bool VEC = !SH && (T % N == 0);
+};
+
 template <int T, typename V, bool SH>
-__device__ void solve_graph(const BatchArgs& a, int gi, Team& tm) {
-  __shared__ double sh[4 * BBS];
-  __shared__ double sh_long[BBS];
-  __shared__ double vals[4 * kMaxTile];
-  __shared__ double s_rho[T], s_alpha[T], s_beta[T], s_bn2[T], s_obn2[T], s_mean[T];
-  __shared__ int s_act[T], s_oact[T], s_it[T], s_itc[T], s_ref[T], s_stat[T];
-  __shared__ int s_nact, s_noact;
+__device__ void solve_graph(const BatchArgs& a, int gi, Team& tm, const Lds& L) {
   const BGraph gd = a.gd[gi];
   const int t = threadIdx.x;
   const int n = gd.n;
@@ -325,11 +417,13 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm) {
   const int k = gd.k;
   const double* Pg = a.P + gd.in_off;
   const double* Qg = a.Q + gd.in_off;
-  // element loop over own rows: e = row*T + c, thread t takes c = t % T
+  double* sh = L.sh;
+  double* vals = L.vals;
+  // scalar element loop: thread t takes column c = t % T (BBS is a multiple of T)
   const int c = t % T;
   const long e0 = (long)lo * T + t;
   const long e1 = (long)hi * T;
-  constexpr int STEP = BBS;       // multiple of T: column fixed per thread
+  constexpr int STEP = BBS;
 
   // (1) delta = P - Q and its mean
   {
@@ -341,13 +435,13 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm) {
       acc[0][0] += d;
     }
     reduce_cols<1>(tm, acc, T, sh, vals);
-    if (t < T) s_mean[t] = vals[t] / (double)n;
+    if (t < T) L.mean[t] = vals[t] / (double)n;
     __syncthreads();
   }
   // (2) delta_bar, ||delta_bar||^2, x = 0
   {
     double acc[1][1] = {{0.0}};
-    const double mc = s_mean[c];
+    const double mc = L.mean[c];
     for (long e = e0; e < e1; e += STEP) {
       const double v = b64[e] - mc;
       b64[e] = v;
@@ -356,51 +450,50 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm) {
     }
     reduce_cols<1>(tm, acc, T, sh, vals);
     if (t < T) {
-      s_obn2[t] = vals[t];
-      s_oact[t] = (t < k && vals[t] > 0.0) ? 1 : 0;
-      s_it[t] = 0;
-      s_ref[t] = 0;
-      s_stat[t] = kStOk;
+      L.obn2[t] = vals[t];
+      L.oact[t] = (t < k && vals[t] > 0.0) ? 1 : 0;
+      L.it[t] = 0;
+      L.ref[t] = 0;
+      L.stat[t] = kStOk;
     }
     __syncthreads();
   }
   // (3) refinement
   for (int step = 0; step <= a.max_refine; ++step) {
-    double mr = 0.0;
     if (step > 0) {
       double acc[4][1] = {{0.0}, {0.0}, {0.0}, {0.0}};
-      block_spmm<double, T, SH, EPI_RESID, 4>(a, gd, lo, hi, x64, r64, b64, acc, sh_long);
+      block_spmm<double, T, SH, EPI_RESID, 4>(a, gd, lo, hi, x64, r64, b64, acc, L.sh_long);
       reduce_cols<4>(tm, acc, T, sh, vals);
       if (t < T) {
         const double m = vals[t] / (double)n;
-        s_mean[t] = m;
+        L.mean[t] = m;
         const double rr = vals[T + t] - (double)n * m * m;   // ||r - mean||^2
-        if (s_oact[t] && rr <= a.rtol2 * s_obn2[t]) s_oact[t] = 0;
+        if (L.oact[t] && rr <= a.rtol2 * L.obn2[t]) L.oact[t] = 0;
       }
       __syncthreads();
-      mr = 1.0;
     }
     if (t == 0) {
       int no = 0;
       for (int q = 0; q < T; ++q) {
-        if (s_oact[q] && s_ref[q] >= a.max_refine) {
-          s_oact[q] = 0;
-          s_stat[q] = kStNoconv;
+        if (L.oact[q] && L.ref[q] >= a.max_refine) {
+          L.oact[q] = 0;
+          L.stat[q] = kStNoconv;
         }
-        no += s_oact[q];
+        no += L.oact[q];
       }
-      s_noact = no;
+      L.cnt[1] = no;
     }
     __syncthreads();
-    if (s_noact == 0) break;
+    if (L.cnt[1] == 0) break;
     // inner set-up from r (or delta_bar on the first step)
     {
       double acc[2][1] = {{0.0}, {0.0}};
-      const double mc = mr != 0.0 ? s_mean[c] : 0.0;
+      const double mc = step > 0 ? L.mean[c] : 0.0;
+      const bool open = L.oact[c] != 0;
       const double* src = step > 0 ? r64 : b64;
       for (long e = e0; e < e1; e += STEP) {
         const long i = e / T;
-        const V rvv = s_oact[c] ? (V)(src[e] - mc) : (V)0;
+        const V rvv = open ? (V)(src[e] - mc) : (V)0;
         const V z = rvv * invd[i];
         rv[e] = rvv;
         cv[e] = (V)0;
@@ -410,11 +503,11 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm) {
       }
       reduce_cols<2>(tm, acc, T, sh, vals);
       if (t < T) {
-        s_rho[t] = vals[t];
-        s_bn2[t] = vals[T + t];
-        s_act[t] = (s_oact[t] && vals[T + t] > 0.0) ? 1 : 0;
-        s_itc[t] = 0;
-        if (s_oact[t]) s_ref[t] += 1;
+        L.rho[t] = vals[t];
+        L.bn2[t] = vals[T + t];
+        L.act[t] = (L.oact[t] && vals[T + t] > 0.0) ? 1 : 0;
+        L.itc[t] = 0;
+        if (L.oact[t]) L.ref[t] += 1;
       }
       __syncthreads();
     }
@@ -422,82 +515,144 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm) {
     for (int it = 0; it < a.max_iter; ++it) {
       if (t == 0) {
         int na = 0;
-        for (int q = 0; q < T; ++q) na += s_act[q];
-        s_nact = na;
+        for (int q = 0; q < T; ++q) na += L.act[q];
+        L.cnt[0] = na;
       }
       __syncthreads();
-      if (s_nact == 0) break;
+      if (L.cnt[0] == 0) break;
       {
         double acc[1][1] = {{0.0}};
-        block_spmm<V, T, SH, EPI_CG, 1>(a, gd, lo, hi, pv, qv, nullptr, acc, sh_long);
+        block_spmm<V, T, SH, EPI_CG, 1>(a, gd, lo, hi, pv, qv, nullptr, acc, L.sh_long);
         reduce_cols<1>(tm, acc, T, sh, vals);
         if (t < T) {
           double al = 0.0;
-          if (s_act[t]) {
+          if (L.act[t]) {
             const double sg = vals[t];
             if (!(sg > 0.0) || !isfinite(sg)) {
-              s_act[t] = 0;
-              s_oact[t] = 0;
-              s_stat[t] = kStBreak;
+              L.act[t] = 0;
+              L.oact[t] = 0;
+              L.stat[t] = kStBreak;
             } else {
-              al = s_rho[t] / sg;
+              al = L.rho[t] / sg;
             }
           }
-          s_alpha[t] = al;
+          L.alpha[t] = al;
         }
         __syncthreads();
       }
       {
-        double acc[2][1] = {{0.0}, {0.0}};
-        const V al = (V)s_alpha[c];
-        for (long e = e0; e < e1; e += STEP) {
-          const long i = e / T;
-          const V pe = vld<SH>(&pv[e]);
-          const V re = rv[e] - al * qv[e];
-          cv[e] = cv[e] + al * pe;
-          rv[e] = re;
-          const double rd = (double)re;
-          acc[0][0] += rd * rd * (double)invd[i];
-          acc[1][0] += rd * rd;
+        using S = Stream<V, T, SH>;
+        constexpr int N = S::N;
+        double acc[2][N];
+#pragma unroll
+        for (int v = 0; v < N; ++v) acc[0][v] = acc[1][v] = 0.0;
+        if constexpr (S::VEC) {
+          using VT = typename Vec16<V>::type;
+          V al[N];
+#pragma unroll
+          for (int v = 0; v < N; ++v) al[v] = (V)L.alpha[(t * N + v) % T];
+          const long i0 = (long)lo * T / N, i1 = (long)hi * T / N;
+          for (long i = i0 + t; i < i1; i += BBS) {
+            VT pvv = reinterpret_cast<const VT*>(pv)[i];
+            VT qvv = reinterpret_cast<const VT*>(qv)[i];
+            VT rvv = reinterpret_cast<const VT*>(rv)[i];
+            VT cvv = reinterpret_cast<const VT*>(cv)[i];
+            const V iv = invd[(i * N) / T];       // T >= N: one row per vector
+            V* ps = reinterpret_cast<V*>(&pvv);
+            V* qs = reinterpret_cast<V*>(&qvv);
+            V* rs = reinterpret_cast<V*>(&rvv);
+            V* cs = reinterpret_cast<V*>(&cvv);
+#pragma unroll
+            for (int v = 0; v < N; ++v) {
+              cs[v] += al[v] * ps[v];
+              rs[v] -= al[v] * qs[v];
+              const double rd = (double)rs[v];
+              acc[0][v] += rd * rd * (double)iv;
+              acc[1][v] += rd * rd;
+            }
+            reinterpret_cast<VT*>(cv)[i] = cvv;
+            reinterpret_cast<VT*>(rv)[i] = rvv;
+          }
+        } else {
+          const V al = (V)L.alpha[c];
+          for (long e = e0; e < e1; e += STEP) {
+            const long i = e / T;
+            const V pe = vld<SH>(&pv[e]);
+            const V re = rv[e] - al * qv[e];
+            cv[e] = cv[e] + al * pe;
+            rv[e] = re;
+            const double rd = (double)re;
+            acc[0][0] += rd * rd * (double)invd[i];
+            acc[1][0] += rd * rd;
+          }
         }
-        reduce_cols<2>(tm, acc, T, sh, vals);
+        // fold the N entries of a thread onto its columns, then reduce
+        double acc1[2][1];
+        if constexpr (S::VEC) {
+          // vectors are used only by single-block graphs (lo = 0), so thread
+          // t's entry v is column (t*N + v) % T
+          block_reduce_vec<2, N>(acc, T, sh, vals);
+          (void)acc1;
+        } else {
+          acc1[0][0] = acc[0][0];
+          acc1[1][0] = acc[1][0];
+          reduce_cols<2>(tm, acc1, T, sh, vals);
+        }
         if (t < T) {
           double be = 0.0;
-          if (s_act[t]) {
+          if (L.act[t]) {
             const double rz = vals[t], rr = vals[T + t];
-            s_it[t] += 1;
-            s_itc[t] += 1;
-            if (rr <= a.irtol2 * s_bn2[t]) {
-              s_act[t] = 0;
-            } else if (s_itc[t] >= a.max_iter) {
-              s_act[t] = 0;
+            L.it[t] += 1;
+            L.itc[t] += 1;
+            if (rr <= a.irtol2 * L.bn2[t]) {
+              L.act[t] = 0;
+            } else if (L.itc[t] >= a.max_iter) {
+              L.act[t] = 0;
             } else if (!(rz > 0.0) || !isfinite(rz)) {
-              s_act[t] = 0;
-              s_oact[t] = 0;
-              s_stat[t] = kStBreak;
+              L.act[t] = 0;
+              L.oact[t] = 0;
+              L.stat[t] = kStBreak;
             } else {
-              be = rz / s_rho[t];
-              s_rho[t] = rz;
+              be = rz / L.rho[t];
+              L.rho[t] = rz;
             }
           }
-          s_beta[t] = be;
+          L.beta[t] = be;
         }
         __syncthreads();
       }
       {
-        const V be = (V)s_beta[c];
-        const bool act = s_act[c] != 0;
-        for (long e = e0; e < e1; e += STEP) {
-          if (!act) break;
-          const long i = e / T;
-          vst<SH>(&pv[e], rv[e] * invd[i] + be * vld<SH>(&pv[e]));
+        using S = Stream<V, T, SH>;
+        constexpr int N = S::N;
+        if constexpr (S::VEC) {
+          using VT = typename Vec16<V>::type;
+          V be[N];
+#pragma unroll
+          for (int v = 0; v < N; ++v) be[v] = (V)L.beta[(t * N + v) % T];
+          const long i0 = (long)lo * T / N, i1 = (long)hi * T / N;
+          for (long i = i0 + t; i < i1; i += BBS) {
+            VT pvv = reinterpret_cast<const VT*>(pv)[i];
+            const VT rvv = reinterpret_cast<const VT*>(rv)[i];
+            const V iv = invd[(i * N) / T];
+            V* ps = reinterpret_cast<V*>(&pvv);
+            const V* rs = reinterpret_cast<const V*>(&rvv);
+#pragma unroll
+            for (int v = 0; v < N; ++v) ps[v] = rs[v] * iv + be[v] * ps[v];
+            reinterpret_cast<VT*>(pv)[i] = pvv;
+          }
+        } else {
+          const V be = (V)L.beta[c];
+          for (long e = e0; e < e1; e += STEP) {
+            const long i = e / T;
+            vst<SH>(&pv[e], rv[e] * invd[i] + be * vld<SH>(&pv[e]));
+          }
         }
         team_sync(tm);
       }
     }
     // x += c (FP64)
     for (long e = e0; e < e1; e += STEP) {
-      if (s_stat[c] == kStOk) vst<SH>(&x64[e], vld<SH>(&x64[e]) + (double)cv[e]);
+      if (L.stat[c] == kStOk) vst<SH>(&x64[e], vld<SH>(&x64[e]) + (double)cv[e]);
     }
     team_sync(tm);
   }
@@ -506,26 +661,26 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm) {
     double acc[1][1] = {{0.0}};
     for (long e = e0; e < e1; e += STEP) acc[0][0] += vld<SH>(&x64[e]);
     reduce_cols<1>(tm, acc, T, sh, vals);
-    if (t < T) s_mean[t] = vals[t] / (double)n;
+    if (t < T) L.mean[t] = vals[t] / (double)n;
     __syncthreads();
-    const double mc = s_mean[c];
+    const double mc = L.mean[c];
     for (long e = e0; e < e1; e += STEP) vst<SH>(&x64[e], vld<SH>(&x64[e]) - mc);
     team_sync(tm);
   }
   {
     double acc[4][1] = {{0.0}, {0.0}, {0.0}, {0.0}};
-    block_spmm<double, T, SH, EPI_RESID, 4>(a, gd, lo, hi, x64, r64, b64, acc, sh_long);
+    block_spmm<double, T, SH, EPI_RESID, 4>(a, gd, lo, hi, x64, r64, b64, acc, L.sh_long);
     reduce_cols<4>(tm, acc, T, sh, vals);
   }
   if (tm.rank == 0 && t < k) {
-    const double bb = s_obn2[t];
+    const double bb = L.obn2[t];
     const double bx = vals[2 * T + t], xr = vals[3 * T + t], rr = vals[T + t];
     double dsq = bb > 0.0 ? bx + xr : 0.0;
     a.d_out[gd.out_off + t] = sqrt(dsq > 0.0 ? dsq : 0.0);
     nvd_pair_info pi;
-    pi.status = s_stat[t];
-    pi.iters = s_it[t];
-    pi.refine_steps = s_ref[t];
+    pi.status = L.stat[t];
+    pi.iters = L.it[t];
+    pi.refine_steps = L.ref[t];
     pi.reserved = 0;
     pi.rel_res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
     pi.dsq_plain = bb > 0.0 ? bx : 0.0;
@@ -543,7 +698,26 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm) {
 
 template <int T, typename V>
 __global__ __launch_bounds__(BBS) void k_batch(BatchArgs a) {
+  __shared__ double lds_d[4 * BBS + BBS + 4 * kMaxTile + 6 * kMaxTile];
+  __shared__ int lds_i[6 * kMaxTile + 2];
   __shared__ int s_unit;
+  Lds L;
+  L.sh = lds_d;
+  L.sh_long = lds_d + 4 * BBS;
+  L.vals = L.sh_long + BBS;
+  L.rho = L.vals + 4 * kMaxTile;
+  L.alpha = L.rho + kMaxTile;
+  L.beta = L.alpha + kMaxTile;
+  L.bn2 = L.beta + kMaxTile;
+  L.obn2 = L.bn2 + kMaxTile;
+  L.mean = L.obn2 + kMaxTile;
+  L.act = lds_i;
+  L.oact = lds_i + kMaxTile;
+  L.it = lds_i + 2 * kMaxTile;
+  L.itc = lds_i + 3 * kMaxTile;
+  L.ref = lds_i + 4 * kMaxTile;
+  L.stat = lds_i + 5 * kMaxTile;
+  L.cnt = lds_i + 6 * kMaxTile;
   const int b = blockIdx.x;
   const int team = a.team_of_block[b];
   int gi = a.team_graph[team];
@@ -558,7 +732,10 @@ __global__ __launch_bounds__(BBS) void k_batch(BatchArgs a) {
   tm.parity = 0;
   tm.err = a.err;
   if (gi >= 0) {
-    solve_graph<T, V, true>(a, gi, tm);
+    if (tm.S > 1)
+      solve_graph<T, V, true>(a, gi, tm, L);
+    else
+      solve_graph<T, V, false>(a, gi, tm, L);
   }
   // then the pool, one graph per block
   Team solo = tm;
@@ -573,7 +750,7 @@ __global__ __launch_bounds__(BBS) void k_batch(BatchArgs a) {
     const int u = s_unit;
     __syncthreads();
     if (u < 0) break;
-    solve_graph<T, V, false>(a, u, solo);
+    solve_graph<T, V, false>(a, u, solo, L);
   }
 }
 
@@ -641,6 +818,8 @@ struct nvd_batch {
   int64_t replays = 0;
   int64_t captures = 0;
   int64_t eager = 0;
+  // CG iterations per graph measured on the previous call (work plan weights)
+  std::vector<double> it_est;
 };
 
 static void batch_drop_graph(nvd_batch* b) {
@@ -682,6 +861,7 @@ nvd_status nvd_batch_create(int32_t G, nvd_graph* const* graphs, void* stream, n
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   nvd_batch* b = new nvd_batch();
   b->G = G;
+  b->it_est.assign(G, 20.0);
   for (int i = 0; i < G; ++i) {
     if (!graphs[i]) {
       delete b;
@@ -818,7 +998,8 @@ static BatchPlan make_plan(const nvd_batch* b, const std::vector<int>& ks, int T
   std::vector<double> w(G);
   double W = 0.0;
   for (int i = 0; i < G; ++i) {
-    w[i] = (ks[i] > 0) ? ((double)b->nnz[i] + 3.0 * b->n[i]) * T : 0.0;
+    // per-iteration traffic x iterations (measured on the previous call)
+    w[i] = (ks[i] > 0) ? ((double)b->nnz[i] + 3.0 * b->n[i]) * T * (b->it_est[i] + 4.0) : 0.0;
     W += w[i];
   }
   std::vector<int> order(G);
@@ -926,6 +1107,10 @@ static nvd_status run_batch(nvd_batch* b, const std::vector<int>& ks, const doub
   hp.insert(hp.end(), pl.team_graph.begin(), pl.team_graph.end());
   hp.insert(hp.end(), pl.pool.begin(), pl.pool.end());
   hp.resize(plan_ints, 0);   // team counters follow (as unsigned)
+  // the plan's sizes are baked into a captured launch: part of its key
+  key.push_back(pl.nteams);
+  key.push_back((long)pl.pool.size());
+  key.insert(key.end(), hp.begin(), hp.end());
   NVD_HIP(hipMemcpyAsync(b->plan_buf, hp.data(), sizeof(int) * plan_ints, hipMemcpyHostToDevice, s));
   NVD_HIP(hipMemcpyAsync(b->gd, gd.data(), sizeof(BGraph) * G, hipMemcpyHostToDevice, s));
   int* pb = b->plan_buf;
@@ -1022,6 +1207,15 @@ static nvd_status run_batch(nvd_batch* b, const std::vector<int>& ks, const doub
   if (info_host)
     NVD_HIP(hipMemcpyAsync(info_host, b->info, sizeof(nvd_pair_info) * K, hipMemcpyDeviceToHost, s));
   NVD_HIP(hipStreamSynchronize(s));
+  if (info_host) {
+    int off = 0;
+    for (int i = 0; i < G; ++i) {
+      int itmax = 0;
+      for (int j = 0; j < ks[i]; ++j) itmax = std::max(itmax, info_host[off + j].iters);
+      if (itmax > 0) b->it_est[i] = itmax;
+      off += ks[i];
+    }
+  }
   if (*b->h_err) {
     set_error("batched solver: a team barrier timed out (blocks not co-resident?)");
     return NVD_E_DEVICE;
