@@ -209,7 +209,7 @@ struct Lds {
   double* sh;        // [4*BBS]
   double* sh_long;   // [BBS]
   double* vals;      // [4*kMaxTile]
-  double *rho, *alpha, *beta, *bn2, *obn2, *mean;   // [kMaxTile] each
+  double *rho, *alpha, *beta, *bn2, *obn2, *mean, *itol2;   // [kMaxTile] each
   int *act, *oact, *it, *itc, *ref, *stat;          // [kMaxTile] each
   int* cnt;          // [2]: active, open
 };
@@ -508,6 +508,9 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm, const Lds& L) 
         L.act[t] = (L.oact[t] && vals[T + t] > 0.0) ? 1 : 0;
         L.itc[t] = 0;
         if (L.oact[t]) L.ref[t] += 1;
+        // inner tolerance relaxed to what this step still needs
+        const double need2 = vals[T + t] > 0.0 ? 0.09 * a.rtol2 * L.obn2[t] / vals[T + t] : 0.0;
+        L.itol2[t] = need2 > a.irtol2 ? (need2 < 0.25 ? need2 : 0.25) : a.irtol2;
       }
       __syncthreads();
     }
@@ -604,7 +607,7 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm, const Lds& L) 
             const double rz = vals[t], rr = vals[T + t];
             L.it[t] += 1;
             L.itc[t] += 1;
-            if (rr <= a.irtol2 * L.bn2[t]) {
+            if (rr <= L.itol2[t] * L.bn2[t]) {
               L.act[t] = 0;
             } else if (L.itc[t] >= a.max_iter) {
               L.act[t] = 0;
@@ -698,7 +701,7 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm, const Lds& L) 
 
 template <int T, typename V>
 __global__ __launch_bounds__(BBS) void k_batch(BatchArgs a) {
-  __shared__ double lds_d[4 * BBS + BBS + 4 * kMaxTile + 6 * kMaxTile];
+  __shared__ double lds_d[4 * BBS + BBS + 4 * kMaxTile + 7 * kMaxTile];
   __shared__ int lds_i[6 * kMaxTile + 2];
   __shared__ int s_unit;
   Lds L;
@@ -711,6 +714,7 @@ __global__ __launch_bounds__(BBS) void k_batch(BatchArgs a) {
   L.bn2 = L.beta + kMaxTile;
   L.obn2 = L.bn2 + kMaxTile;
   L.mean = L.obn2 + kMaxTile;
+  L.itol2 = L.mean + kMaxTile;
   L.act = lds_i;
   L.oact = lds_i + kMaxTile;
   L.it = lds_i + 2 * kMaxTile;

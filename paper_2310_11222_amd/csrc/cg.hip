@@ -148,6 +148,7 @@ __global__ __launch_bounds__(kBS) void k_proj_init(int n, long cap, ProjSrc src,
     cs->it_cur[t] = 0;
     cs->refine[t] = 0;
     cs->status[t] = kStOk;
+    cs->itol2[t] = 0.0;
   }
   recount_active(cs, T);
 }
@@ -231,7 +232,8 @@ __global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__
       const double rr = vals[T + t];
       cs->iters[t] += 1;
       cs->it_cur[t] += 1;
-      if (rr <= rtol2 * cs->bnorm2[t]) {
+      const double tol2 = cs->itol2[t] > 0.0 ? cs->itol2[t] : rtol2;
+      if (rr <= tol2 * cs->bnorm2[t]) {
         cs->active[t] = 0;
       } else if (cs->it_cur[t] >= max_iter) {
         cs->active[t] = 0;
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__
         be = rz / cs->rho[t];
         cs->rho[t] = rz;
       }
-      vals[t] = cs->active[t] ? rr / (rtol2 * cs->bnorm2[t]) : 0.0;
+      vals[t] = cs->active[t] ? rr / (tol2 * cs->bnorm2[t]) : 0.0;
     } else {
       vals[t] = 0.0;
     }
@@ -295,8 +297,8 @@ __global__ __launch_bounds__(kBS) void k_direction(int n, long cap, V* __restric
 __global__ __launch_bounds__(kBS) void k_inner_init_any(int T, int n, long cap, const double* src,
                                                         MeanSrc m, const float* invd32, float* x32,
                                                         float* r32, float* p32, float* q32,
-                                                        double rtol2, int max_refine, int first,
-                                                        ColState* cs, GridRed red) {
+                                                        double rtol2, double irtol2, int max_refine,
+                                                        int first, ColState* cs, GridRed red) {
   __shared__ double sh[3 * kBS];
   __shared__ double vals[3 * kMaxTile];
   const int t = threadIdx.x;
@@ -348,6 +350,10 @@ __global__ __launch_bounds__(kBS) void k_inner_init_any(int T, int n, long cap, 
     cs->bnorm2[t] = vals[2 * T + t];
     cs->rho[t] = vals[T + t];
     cs->it_cur[t] = 0;
+    // inner tolerance: inner_rtol, relaxed to what this step still needs
+    // (a reduction to 0.3 rtol ||delta_bar|| / ||r||) when that is less
+    const double need2 = vals[t] > 0.0 ? 0.09 * rtol2 * cs->obnorm2[t] / vals[t] : 0.0;
+    cs->itol2[t] = need2 > irtol2 ? (need2 < 0.25 ? need2 : 0.25) : irtol2;
     cs->alpha[t] = 0.0;
     cs->beta[t] = 0.0;
   }
@@ -421,6 +427,7 @@ __global__ __launch_bounds__(kBS) void k_restart(int n, long cap, const double* 
     cs->rho[t] = vals[t];
     cs->active[t] = cs->oactive[t] && vals[t] > 0.0;
     cs->bnorm2[t] = cs->obnorm2[t];
+    cs->itol2[t] = 0.0;
     cs->it_cur[t] = 0;
     cs->alpha[t] = 0.0;
     cs->beta[t] = 0.0;
@@ -723,8 +730,8 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
         src = ws->r64;
       }
       k_inner_init_any<<<grid, kBS, 0, s>>>(T, n, cap, src, mr, g->invd32, ws->x32, ws->r32,
-                                            ws->p32, ws->q32, rtol2, sp.max_refine, first ? 1 : 0,
-                                            ws->cs, ws->red);
+                                            ws->p32, ws->q32, rtol2, irtol2, sp.max_refine,
+                                            first ? 1 : 0, ws->cs, ws->red);
       NVD_HIP(hipGetLastError());
       first = false;
       int no = 0;

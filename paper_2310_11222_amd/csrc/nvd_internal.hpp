@@ -42,6 +42,7 @@ struct ColState {
   double obnorm2[kMaxTile]; // ||delta_bar||^2 (outer right-hand side)
   double orr[kMaxTile];     // latest outer ||r||^2 (projected, FP64)
   double mean[kMaxTile];    // mean removed by the last projection (1 component)
+  double itol2[kMaxTile];   // stop threshold of the running CG: ||r||^2 <= itol2 * bnorm2
   double dots[kMaxDots][kMaxTile];  // dots of the last residual pass
   int active[kMaxTile];     // running CG still iterating
   int oactive[kMaxTile];    // pair not yet converged (outer level)
