@@ -38,6 +38,29 @@ def load_golden():
     return np.array([float(v) for v in g["d"]])
 
 
+def load_traffic(tile):
+    """HBM bytes per launch of the FP32 SpMM from the committed counter
+    profile, if it was taken on the current kernel source at this tile."""
+    import hashlib
+    p = os.path.join(ROOT, "profiles", "k_spmm_f32_ba1e6_k64_traffic.md")
+    if not os.path.exists(p):
+        return None
+    fields = {}
+    for line in open(p):
+        if ":" in line and not line.startswith(("#", " ", "|")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for src in ("paper_2310_11222_amd/csrc/spmm.hip", "paper_2310_11222_amd/csrc/device_common.hpp",
+                "paper_2310_11222_amd/csrc/nvd_internal.hpp"):
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if fields.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    if f"k_spmm<float, {tile}," not in fields.get("kernel", ""):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def load_golden_batch():
     p = os.path.join(ROOT, "tests", "golden", "c3_expected.json")
     if not os.path.exists(p):
@@ -130,6 +153,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--inner-rtol", type=float, default=1e-5)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 512 MiB device copy first (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -142,6 +167,14 @@ def main():
     from nvdgen import workload
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy: 536870912 bytes read, 536870912 bytes written")
     log("generating workload")
     t0 = time.perf_counter()
     w = workload(2)
@@ -214,12 +247,13 @@ def main():
                 "gbs": bytes_per / (avg_ms * 1e-3) / 1e9, "launches": p["launches"],
                 "ms_total": p["ms"]}
 
+    tile_used = args.tile or dg.tuning(K, "mixed")[0]
     kinds = {k: kern(k) for k in prof}
     dom = max((k for k in kinds if kinds[k]), key=lambda k: kinds[k]["ms_total"])
     sp = kinds["spmm_f32"]
-    roof = {"kernel": "k_spmm<float> (EPI_CG, Laplacian apply + p^T q)", "bound": "hbm",
+    roof = {"kernel": f"k_spmm<float, {tile_used}> (EPI_CG: q = L p and p^T q)", "bound": "hbm",
             "achieved": round(sp["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(sp["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(sp["gbs"] / HBM_PEAK_GBS, 4), "traffic": load_traffic(tile_used),
             "bytes_per_launch": sp["bytes_per_launch"], "avg_launch_us": round(sp["avg_us"], 2)}
     log(f"kernels: " + json.dumps({k: (round(v['gbs'], 1), round(v['ms_total'], 2)) for k, v in kinds.items() if v}))
 
@@ -253,7 +287,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ba_n1e6_m3_unit_k64", "n": g.n, "nnz": g.nnz, "pairs": K,
                    "rtol": rtol, "precision": "mixed (FP32 CG + FP64 refinement)",
-                   "inner_rtol": args.inner_rtol, "tile": args.tile or "auto"},
+                   "inner_rtol": args.inner_rtol, "tile": tile_used,
+                   "tile_chosen_by": "option" if args.tile else "autotuner"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp64_path": {"value": round(value64, 2), "unit": "distances/s",
