@@ -1,0 +1,59 @@
+"""Full-size parity, in the launch configuration bench.py times, against
+distances the CPU oracle stored under tests/golden/ (written by
+tests/golden/make_golden.py, which calls only the oracle)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from nvdgen import workload
+
+from gpu_helpers import say, rel_err
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden(name):
+    p = os.path.join(HERE, "golden", f"{name}_expected.json")
+    if not os.path.exists(p):
+        pytest.skip(f"{name} oracle values not stored")
+    g = json.load(open(p))
+    return np.array([float(v) for v in g["d"]]), g
+
+
+@pytest.mark.parametrize("precision,tol", [("mixed", 1e-6), ("fp64", 1e-8)])
+def test_ba_1e6_all_64_pairs(precision, tol):
+    import torch
+    import paper_2310_11222_amd as nvd
+    ref, meta = _golden("c2")
+    w = workload(2)
+    g = w.graphs[0]
+    assert g.n == meta["n"] and g.nnz == meta["nnz"]
+    say("full c2", precision)
+    dg = nvd.Graph(g.row_ptr, g.col_idx, g.w)
+    P = torch.as_tensor(w.P[0]).cuda()
+    Q = torch.as_tensor(w.Q[0]).cuda()
+    d, _, info = dg.distances(P, Q, precision=precision, rtol=w.rtol)
+    e = rel_err(d.cpu().numpy(), ref)
+    assert e.max() <= tol, e.max()
+    assert all(i["status"] == 0 and i["rel_res"] <= 1.01 * w.rtol for i in info)
+
+
+def test_batch_512_graphs_all_4096_pairs():
+    import torch
+    import paper_2310_11222_amd as nvd
+    ref, meta = _golden("c3")
+    w = workload(3)
+    assert len(w.graphs) == meta["graphs"] and sum(g.n for g in w.graphs) == meta["n_total"]
+    say("full c3 batch", meta["n_total"])
+    dgs = [nvd.Graph(g.row_ptr, g.col_idx, g.w) for g in w.graphs]
+    batch = nvd.Batch(dgs)
+    packed = batch.pack(w.P, w.Q)
+    out = torch.empty(int(packed[0].sum()), dtype=torch.float64, device="cuda")
+    for rep in range(2):               # direct or captured launch, then a replay
+        d, _, info = batch.distances(None, None, packed=packed, out=out, rtol=w.rtol)
+        e = rel_err(d.cpu().numpy(), ref)
+        assert e.max() <= 1e-6, (rep, e.max())
+        assert all(i["status"] == 0 for i in info)
