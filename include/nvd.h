@@ -239,6 +239,13 @@ nvd_status nvd_batch_destroy(nvd_batch* b);
  * refused by the runtime). */
 nvd_status nvd_batch_query(const nvd_batch* b, int64_t* captures,
                            int64_t* replays, int64_t* eager);
+/* Per-graph timing of the last nvd_batch_distances call made with the
+ * environment variable NVD_BATCH_TRACE=1: start_end (host int64 [2G])
+ * receives device wall-clock ticks (100 MHz) at the start and end of each
+ * graph's solve, team_size (host int32 [G]) the number of blocks that solved
+ * it.  NVD_E_ARG if no trace was recorded. */
+nvd_status nvd_batch_trace(const nvd_batch* b, int32_t G, int64_t* start_end,
+                           int32_t* team_size);
 nvd_status nvd_batch_distances(nvd_batch* b, const int32_t* k_per_graph,
                                const double* P, const double* Q,
                                const nvd_opts* opts, double* d_out,

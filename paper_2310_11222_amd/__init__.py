@@ -220,6 +220,15 @@ class Batch:
         check(load().nvd_batch_query(self._h, C.byref(c), C.byref(r), C.byref(e)), "nvd_batch_query")
         return {"captures": c.value, "replays": r.value, "eager": e.value}
 
+    def trace(self):
+        """(start_end ticks (G, 2), team sizes (G,)) of the last traced call."""
+        G = len(self.graphs)
+        se = np.zeros((G, 2), dtype=np.int64)
+        ts = np.zeros(G, dtype=np.int32)
+        check(load().nvd_batch_trace(self._h, G, se.ctypes.data_as(C.c_void_p),
+                                     ts.ctypes.data_as(C.c_void_p)), "nvd_batch_trace")
+        return se, ts
+
     @staticmethod
     def pack(P_list, Q_list):
         """Graph-major packed device copies of per-graph (n_g, k_g) blocks."""

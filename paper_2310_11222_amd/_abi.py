@@ -59,6 +59,7 @@ SIGNATURES = {
     "nvd_batch_destroy": (_I32, [_P]),
     "nvd_batch_distances": (_I32, [_P, _P, _P, _P, C.POINTER(NvdOpts), _P, _P, _P, _P]),
     "nvd_batch_query": (_I32, [_P, _P, _P, _P]),
+    "nvd_batch_trace": (_I32, [_P, _I32, _P, _P]),
     "nvd_tune_query": (_I32, [_P, _I32, _I32, _P, _P, _P]),
     "nvd_prof_enable": (_I32, [_I32]),
     "nvd_prof_read": (_I32, [_P, _P, _P]),
@@ -77,12 +78,15 @@ class NvdError(RuntimeError):
         self.status = status
 
 
-def load(path: str = LIB_PATH):
-    """Load libnvd.so and declare every entry point.  Raises loudly if the
-    library has not been built: there is no fallback path."""
+def load(path: str = None):
+    """Load libnvd.so (or the build named by the environment variable
+    NVD_LIBRARY) and declare every entry point.  Raises loudly if the library
+    has not been built: there is no fallback path."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = os.environ.get("NVD_LIBRARY", LIB_PATH)
     if not os.path.exists(path):
         raise RuntimeError(
             f"libnvd.so not found at {path}; build it first with "

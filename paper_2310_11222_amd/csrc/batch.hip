@@ -81,6 +81,7 @@ struct BatchArgs {
   double rtol2, irtol2;
   int max_iter, max_refine;
   int* err;
+  unsigned long long* trace;  // [2G] start/end wall-clock ticks per graph, or null
 };
 
 template <bool SH, typename V>
@@ -197,11 +198,16 @@ __device__ __forceinline__ void block_reduce_vec(double (&acc)[ND][N], int T, do
   __syncthreads();
 }
 
-template <int T>
+// Lane layout of the block SpMM: G = T*NL lanes per row; R rows carried at
+// once per lane group (4 for the FP32 inner SpMM, 2 for the FP64 residual;
+// more rows spill registers at 4 waves per SIMD); MB gathers per lane per
+// batch.
+template <int T, typename V = float>
 struct BLanes {
   static constexpr int NL = T >= 16 ? 1 : (T == 8 ? 2 : (T == 4 ? 4 : 8));
   static constexpr int G = T * NL;
-  static constexpr int R = 4;                 // rows carried at once per lane group
+  static constexpr int R = sizeof(V) == 4 ? 4 : 2;
+  static constexpr int MB = 4;
 };
 
 // Working storage of one block (kernel-level LDS, shared by both code paths).
@@ -220,14 +226,15 @@ struct Lds {
 // Short rows: groups of G = T*NL lanes, R rows per group at once, neighbour
 // indices loaded G at a time and shuffled out so gathers issue back to back.
 template <typename V, int T, bool SH, int EPI, int ND>
-__device__ void block_spmm(const BatchArgs& a, const BGraph& gd, int lo, int hi, const V* x,
+__device__ __noinline__ void block_spmm(const BatchArgs& a, const BGraph& gd, int lo, int hi, const V* x,
                            V* y, const double* b, double (&acc)[ND][1], double* sh_long) {
-  constexpr int NL = BLanes<T>::NL;
-  constexpr int G = BLanes<T>::G;
-  constexpr int R = BLanes<T>::R;
+  using LN = BLanes<T, V>;
+  constexpr int NL = LN::NL;
+  constexpr int G = LN::G;
+  constexpr int R = LN::R;
   constexpr int RW = 64 / G;
   constexpr int MM = G / NL;
-  constexpr int MB = MM < 8 ? MM : 8;
+  constexpr int MB = MM < LN::MB ? MM : LN::MB;
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
@@ -394,10 +401,11 @@ struct Stream {
 };
 
 template <int T, typename V, bool SH>
-__device__ void solve_graph(const BatchArgs& a, int gi, Team& tm, const Lds& L) {
+__device__ __noinline__ void solve_graph(const BatchArgs& a, int gi, Team& tm, const Lds& L) {
   const BGraph gd = a.gd[gi];
   const int t = threadIdx.x;
   const int n = gd.n;
+  if (a.trace && tm.rank == 0 && t == 0) a.trace[2 * gi] = wall_clock64();
   const int* rp = a.rp + gd.rp_off;
   const int lo = split_row(rp, n, tm.rank, tm.S);
   const int hi = split_row(rp, n, tm.rank + 1, tm.S);
@@ -550,31 +558,51 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm, const Lds& L) 
 #pragma unroll
         for (int v = 0; v < N; ++v) acc[0][v] = acc[1][v] = 0.0;
         if constexpr (S::VEC) {
+          // U vectors per thread per pass: all loads issued before any use
           using VT = typename Vec16<V>::type;
+          constexpr int U = 2;
           V al[N];
 #pragma unroll
           for (int v = 0; v < N; ++v) al[v] = (V)L.alpha[(t * N + v) % T];
-          const long i0 = (long)lo * T / N, i1 = (long)hi * T / N;
-          for (long i = i0 + t; i < i1; i += BBS) {
-            VT pvv = reinterpret_cast<const VT*>(pv)[i];
-            VT qvv = reinterpret_cast<const VT*>(qv)[i];
-            VT rvv = reinterpret_cast<const VT*>(rv)[i];
-            VT cvv = reinterpret_cast<const VT*>(cv)[i];
-            const V iv = invd[(i * N) / T];       // T >= N: one row per vector
-            V* ps = reinterpret_cast<V*>(&pvv);
-            V* qs = reinterpret_cast<V*>(&qvv);
-            V* rs = reinterpret_cast<V*>(&rvv);
-            V* cs = reinterpret_cast<V*>(&cvv);
+          const long i1 = (long)hi * T / N;
+          const VT* __restrict__ P4 = reinterpret_cast<const VT*>(pv);
+          const VT* __restrict__ Q4 = reinterpret_cast<const VT*>(qv);
+          VT* __restrict__ R4 = reinterpret_cast<VT*>(rv);
+          VT* __restrict__ C4 = reinterpret_cast<VT*>(cv);
+          for (long i0 = t; i0 < i1; i0 += (long)U * BBS) {
+            VT pvv[U], qvv[U], rvv[U], cvv[U];
+            V iv[U];
 #pragma unroll
-            for (int v = 0; v < N; ++v) {
-              cs[v] += al[v] * ps[v];
-              rs[v] -= al[v] * qs[v];
-              const double rd = (double)rs[v];
-              acc[0][v] += rd * rd * (double)iv;
-              acc[1][v] += rd * rd;
+            for (int u = 0; u < U; ++u) {
+              const long i = i0 + (long)u * BBS;
+              if (i < i1) {
+                pvv[u] = P4[i];
+                qvv[u] = Q4[i];
+                rvv[u] = R4[i];
+                cvv[u] = C4[i];
+                iv[u] = invd[(i * N) / T];     // T >= N: one row per vector
+              }
             }
-            reinterpret_cast<VT*>(cv)[i] = cvv;
-            reinterpret_cast<VT*>(rv)[i] = rvv;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const long i = i0 + (long)u * BBS;
+              if (i < i1) {
+                V* ps = reinterpret_cast<V*>(&pvv[u]);
+                V* qs = reinterpret_cast<V*>(&qvv[u]);
+                V* rs = reinterpret_cast<V*>(&rvv[u]);
+                V* cs = reinterpret_cast<V*>(&cvv[u]);
+#pragma unroll
+                for (int v = 0; v < N; ++v) {
+                  cs[v] += al[v] * ps[v];
+                  rs[v] -= al[v] * qs[v];
+                  const double rd = (double)rs[v];
+                  acc[0][v] += rd * rd * (double)iv[u];
+                  acc[1][v] += rd * rd;
+                }
+                C4[i] = cvv[u];
+                R4[i] = rvv[u];
+              }
+            }
           }
         } else {
           const V al = (V)L.alpha[c];
@@ -629,19 +657,36 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm, const Lds& L) 
         constexpr int N = S::N;
         if constexpr (S::VEC) {
           using VT = typename Vec16<V>::type;
+          constexpr int U = 2;
           V be[N];
 #pragma unroll
           for (int v = 0; v < N; ++v) be[v] = (V)L.beta[(t * N + v) % T];
-          const long i0 = (long)lo * T / N, i1 = (long)hi * T / N;
-          for (long i = i0 + t; i < i1; i += BBS) {
-            VT pvv = reinterpret_cast<const VT*>(pv)[i];
-            const VT rvv = reinterpret_cast<const VT*>(rv)[i];
-            const V iv = invd[(i * N) / T];
-            V* ps = reinterpret_cast<V*>(&pvv);
-            const V* rs = reinterpret_cast<const V*>(&rvv);
+          const long i1 = (long)hi * T / N;
+          VT* __restrict__ P4 = reinterpret_cast<VT*>(pv);
+          const VT* __restrict__ R4 = reinterpret_cast<const VT*>(rv);
+          for (long i0 = t; i0 < i1; i0 += (long)U * BBS) {
+            VT pvv[U], rvv[U];
+            V iv[U];
 #pragma unroll
-            for (int v = 0; v < N; ++v) ps[v] = rs[v] * iv + be[v] * ps[v];
-            reinterpret_cast<VT*>(pv)[i] = pvv;
+            for (int u = 0; u < U; ++u) {
+              const long i = i0 + (long)u * BBS;
+              if (i < i1) {
+                pvv[u] = P4[i];
+                rvv[u] = R4[i];
+                iv[u] = invd[(i * N) / T];
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const long i = i0 + (long)u * BBS;
+              if (i < i1) {
+                V* ps = reinterpret_cast<V*>(&pvv[u]);
+                const V* rs = reinterpret_cast<const V*>(&rvv[u]);
+#pragma unroll
+                for (int v = 0; v < N; ++v) ps[v] = rs[v] * iv[u] + be[v] * ps[v];
+                P4[i] = pvv[u];
+              }
+            }
           }
         } else {
           const V be = (V)L.beta[c];
@@ -696,11 +741,12 @@ __device__ void solve_graph(const BatchArgs& a, int gi, Team& tm, const Lds& L) 
       if (c < k) a.X[gd.in_off + i * k + c] = vld<SH>(&x64[e]);
     }
   }
+  if (a.trace && tm.rank == 0 && t == 0) a.trace[2 * gi + 1] = wall_clock64();
   __syncthreads();
 }
 
 template <int T, typename V>
-__global__ __launch_bounds__(BBS) void k_batch(BatchArgs a) {
+__global__ __launch_bounds__(BBS, 4) void k_batch(BatchArgs a) {
   __shared__ double lds_d[4 * BBS + BBS + 4 * kMaxTile + 7 * kMaxTile];
   __shared__ int lds_i[6 * kMaxTile + 2];
   __shared__ int s_unit;
@@ -824,6 +870,9 @@ struct nvd_batch {
   int64_t eager = 0;
   // CG iterations per graph measured on the previous call (work plan weights)
   std::vector<double> it_est;
+  // optional per-graph timing of the last call (NVD_BATCH_TRACE=1)
+  unsigned long long* trace = nullptr;
+  std::vector<int> last_team_size;
 };
 
 static void batch_drop_graph(nvd_batch* b) {
@@ -839,7 +888,7 @@ static void batch_free(nvd_batch* b) {
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   void* ptrs[] = {b->rp, b->ci, b->w64, b->w32, b->deg64, b->deg32, b->invd64, b->invd32,
                   b->long_rows, b->b64, b->x64, b->r64, b->cv, b->rv, b->pv, b->qv, b->gd,
-                  b->plan_buf, b->ctr, b->pool_next, b->err, b->part, b->info};
+                  b->plan_buf, b->ctr, b->pool_next, b->err, b->part, b->info, b->trace};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (b->h_err) (void)hipHostFree(b->h_err);
@@ -994,8 +1043,8 @@ static int resident_blocks() {
   return per_cu * cus;
 }
 
-// Teams for graphs above a block's fair share (up to half of the blocks),
-// the rest pooled largest first.
+// Teams for graphs above a block's fair share (up to three quarters of the
+// blocks), the rest pooled largest first.
 static BatchPlan make_plan(const nvd_batch* b, const std::vector<int>& ks, int T, int B) {
   BatchPlan pl;
   const int G = b->G;
@@ -1013,10 +1062,10 @@ static BatchPlan make_plan(const nvd_batch* b, const std::vector<int>& ks, int T
   int used = 0;
   std::vector<int> big;
   for (int gi : order) {
-    if (w[gi] <= 2.0 * share) break;
+    if (w[gi] <= share) break;
     int S = (int)std::ceil(w[gi] / share);
     S = std::min(S, 64);
-    if (used + S > B / 2) break;
+    if (used + S > (3 * B) / 4) break;
     big.push_back(gi);
     pl.team_graph.push_back(gi);
     pl.team_first.push_back(used);
@@ -1159,6 +1208,17 @@ static nvd_status run_batch(nvd_batch* b, const std::vector<int>& ks, const doub
   a.max_iter = o.max_iter;
   a.max_refine = mixed ? o.max_refine : std::max(2, std::min(o.max_refine, 3));
   a.err = b->err;
+  const char* tr = std::getenv("NVD_BATCH_TRACE");
+  if (tr && tr[0] == '1') {
+    if (!b->trace) NVD_TRY(balloc(b, &b->trace, (size_t)2 * G));
+    a.trace = b->trace;
+    key.push_back(1);
+  } else {
+    a.trace = nullptr;
+  }
+  b->last_team_size.assign(G, 1);
+  for (int q = 0; q < pl.nteams; ++q)
+    if (pl.team_graph[q] >= 0) b->last_team_size[pl.team_graph[q]] = pl.team_size[q];
   // the launch sequence: counters reset by a kernel (no memset node), then
   // the persistent kernel
   auto enqueue = [&](hipStream_t q) -> nvd_status {
@@ -1228,6 +1288,21 @@ static nvd_status run_batch(nvd_batch* b, const std::vector<int>& ks, const doub
 }
 
 }  // namespace nvd
+
+extern "C" nvd_status nvd_batch_trace(const nvd_batch* b, int32_t G, int64_t* start_end,
+                                      int32_t* team_size) {
+  if (!b || !start_end || !team_size || G != b->G) {
+    set_error("nvd_batch_trace: bad argument");
+    return NVD_E_ARG;
+  }
+  if (!b->trace) {
+    set_error("nvd_batch_trace: no trace recorded (set NVD_BATCH_TRACE=1 before the call)");
+    return NVD_E_ARG;
+  }
+  NVD_HIP(hipMemcpy(start_end, b->trace, sizeof(int64_t) * 2 * G, hipMemcpyDeviceToHost));
+  for (int i = 0; i < G; ++i) team_size[i] = b->last_team_size.empty() ? 1 : b->last_team_size[i];
+  return NVD_OK;
+}
 
 extern "C" nvd_status nvd_batch_query(const nvd_batch* b, int64_t* captures, int64_t* replays,
                                       int64_t* eager) {

@@ -12,6 +12,9 @@
 //    segment (256/T lanes per column), partial sums reduced in LDS; rows with
 //    several segments combine them in fixed order in the last segment block
 //    to arrive (per-row arrival counter), so results do not depend on timing.
+// The CSR and the output are touched once per pass: they are loaded and
+// stored non-temporally so that they do not push the gathered vector out of
+// the last-level cache.
 // Epilogues fuse the consumer of L X:
 //  * EPI_PLAIN: store Y.
 //  * EPI_CG:    q = L p, store q and reduce sigma_c = p_c^T q_c; the grid's
@@ -46,13 +49,13 @@ __device__ __forceinline__ void spmm_epilogue(const SpmmK<V>& a, int row, int c,
                                               V dg, double bb, double (&acc)[ND][1]) {
   const V yv = dg * own - sum;
   if constexpr (EPI == EPI_PLAIN) {
-    a.y[(long)row * a.ldy + c] = yv;
+    __builtin_nontemporal_store(yv, &a.y[(long)row * a.ldy + c]);
   } else if constexpr (EPI == EPI_CG) {
-    a.y[(long)row * a.ldy + c] = yv;
+    __builtin_nontemporal_store(yv, &a.y[(long)row * a.ldy + c]);
     acc[0][0] += (double)own * (double)yv;
   } else {
     const double rr = bb - (double)yv;
-    a.y[(long)row * a.ldy + c] = (V)rr;
+    __builtin_nontemporal_store((V)rr, &a.y[(long)row * a.ldy + c]);
     acc[0][0] += bb * (double)own;
     acc[1][0] += (double)own * rr;
     acc[2][0] += rr * rr;
@@ -201,9 +204,10 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
         for (int r = 0; r < R; ++r) {
           cnt[r] = deg[r] - off;
           cnt[r] = cnt[r] < 0 ? 0 : (cnt[r] > G ? G : cnt[r]);
-          myc[r] = li < cnt[r] ? a.ci[rs[r] + off + li] : 0;
+          myc[r] = li < cnt[r] ? __builtin_nontemporal_load(&a.ci[rs[r] + off + li]) : 0;
           myw[r] = (V)1;
-          if constexpr (!UNIT) myw[r] = li < cnt[r] ? a.w[rs[r] + off + li] : (V)0;
+          if constexpr (!UNIT)
+            myw[r] = li < cnt[r] ? __builtin_nontemporal_load(&a.w[rs[r] + off + li]) : (V)0;
         }
         int maxcnt = 0;
 #pragma unroll
