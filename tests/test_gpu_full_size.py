@@ -57,3 +57,23 @@ def test_batch_512_graphs_all_4096_pairs():
         e = rel_err(d.cpu().numpy(), ref)
         assert e.max() <= 1e-6, (rep, e.max())
         assert all(i["status"] == 0 for i in info)
+
+
+def test_configuration_model_1e7_16_pairs():
+    """Power-law configuration model, giant component of 1e7 nodes, ~7.6e7
+    stored nonzeros, 16 pairs: FP32 CG + FP64 refinement, distances within
+    1e-6 of the oracle."""
+    import torch
+    import paper_2310_11222_amd as nvd
+    ref, meta = _golden("c5")
+    w = workload(5)
+    g = w.graphs[0]
+    assert g.n == meta["n"] and g.nnz == meta["nnz"]
+    say("full c5", g.n, g.nnz)
+    dg = nvd.Graph(g.row_ptr, g.col_idx, g.w)
+    P = torch.as_tensor(w.P[0]).cuda()
+    Q = torch.as_tensor(w.Q[0]).cuda()
+    d, _, info = dg.distances(P, Q, precision="mixed", rtol=w.rtol)
+    e = rel_err(d.cpu().numpy(), ref)
+    assert e.max() <= 1e-6, e.max()
+    assert all(i["status"] == 0 for i in info)
