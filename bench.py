@@ -42,7 +42,7 @@ def load_traffic(tile):
     """HBM bytes per launch of the FP32 SpMM from the committed counter
     profile, if it was taken on the current kernel source at this tile."""
     import hashlib
-    p = os.path.join(ROOT, "profiles", "k_spmm_f32_ba1e6_k64_traffic.md")
+    p = os.path.join(ROOT, "profiles", f"k_spmm_f32_ba1e6_k64_T{tile}_traffic.md")
     if not os.path.exists(p):
         return None
     fields = {}

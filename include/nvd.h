@@ -183,10 +183,12 @@ nvd_status nvd_distances(nvd_graph* g, int32_t k, const double* P,
                          nvd_pair_info* info, void* stream);
 
 /* ---- tile autotuner --------------------------------------------------------
- * The tile (pairs per SpMM pass) and the neighbour lanes per row that
- * nvd_distances uses for k pairs when opts->tile_k == 0: candidates are
- * timed on this graph on first use (device work on `stream`) and cached in
- * the handle.  Environment variable NVD_TUNE=0 selects a fixed heuristic. */
+ * The tile (pairs per SpMM pass) and the number of lane sub-groups that
+ * share each row's neighbours in the Laplacian apply (nl), which
+ * nvd_distances uses for k pairs when opts->tile_k == 0.  Candidates are
+ * timed on this graph on first use (whole CG iterations; device work on
+ * `stream`) and cached in the handle.  Environment variable NVD_TUNE=0
+ * selects a fixed heuristic. */
 nvd_status nvd_tune_query(nvd_graph* g, int32_t k, int32_t precision,
                           int32_t* tile, int32_t* nl, void* stream);
 

@@ -611,6 +611,117 @@ static nvd_status cg_loop(DevGraph* g, Workspace* ws, int T, V* x, V* r, V* p, V
   return NVD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// timing of one CG iteration, for the autotuner
+// ---------------------------------------------------------------------------
+// The vector passes of an iteration cost more per byte once the tile's
+// vectors no longer fit in the last-level cache, so the tile is chosen on
+// whole iterations (apply, update, direction), not on the apply alone.  The
+// iteration runs on the workspace vectors with a private column state that
+// keeps every column active: r = 1, alpha = 0 (x and r stay put) and a huge
+// rho (beta ~ 0, so p stays bounded), and a negative ||b||^2 so that no
+// column ever counts as converged.
+__global__ void k_tune_state(int T, ColState* cs) {
+  const int t = threadIdx.x;
+  if (t < T) {
+    cs->rho[t] = 1e300;
+    cs->alpha[t] = 0.0;
+    cs->beta[t] = 0.0;
+    cs->bnorm2[t] = -1.0;
+    cs->itol2[t] = 0.0;
+    cs->active[t] = 1;
+    cs->oactive[t] = 1;
+    cs->it_cur[t] = 0;
+    cs->iters[t] = 0;
+    cs->status[t] = kStOk;
+  }
+  if (t == 0) {
+    cs->n_active = T;
+    cs->n_oactive = T;
+    cs->it_max = 0;
+  }
+}
+
+template <typename V>
+__global__ void k_tune_fill(V* v, long cap, V val) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (long)gridDim.x * blockDim.x)
+    v[i] = val;
+}
+
+template <typename V>
+static nvd_status enqueue_tune_iteration(DevGraph* g, Workspace* ws, int T, int nl, ColState* tcs,
+                                         hipStream_t s) {
+  const long cap = (long)padded_cap(g->n, T);
+  const int sgrid = stream_grid(cap / Vec16<V>::N);
+  V* x;
+  V* r;
+  V* p;
+  V* q;
+  const V* invd;
+  if constexpr (sizeof(V) == 8) {
+    x = ws->x64; r = ws->r64; p = ws->p64; q = ws->q64; invd = g->invd64;
+  } else {
+    x = ws->x32; r = ws->r32; p = ws->p32; q = ws->q32; invd = g->invd32;
+  }
+  k_tune_state<<<1, kMaxTile, 0, s>>>(T, tcs);
+  SpmmCall sc{};
+  sc.g = g;
+  sc.prec = sizeof(V) == 8 ? 0 : 1;
+  sc.T = T;
+  sc.nl = nl;
+  sc.x = p;
+  sc.ldx = T;
+  sc.y = q;
+  sc.ldy = T;
+  sc.cs = tcs;
+  sc.epi = EPI_PLAIN;
+  NVD_TRY(launch_spmm(sc, ws->red, s));
+  NVD_TILE_SWITCH(T, (k_update<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, x, r, p, q, invd, 1.0,
+                                                            0x7fffffff, tcs, ws->red)));
+  NVD_TILE_SWITCH(T, (k_direction<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, p, r, invd, tcs)));
+  NVD_HIP(hipGetLastError());
+  return NVD_OK;
+}
+
+template <typename V>
+static nvd_status time_iteration_t(DevGraph* g, int T, int nl, hipStream_t s, float* ms) {
+  Workspace* ws = g->ws;
+  const long cap = (long)padded_cap(g->n, T);
+  ColState* tcs = nullptr;
+  NVD_HIP(hipMalloc(&tcs, sizeof(ColState)));
+  hipEvent_t a = nullptr, b = nullptr;
+  nvd_status st = NVD_OK;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) st = NVD_E_DEVICE;
+  if (st == NVD_OK) {
+    // r = 1 on the n x T tile, padding left at zero
+    V* r = sizeof(V) == 8 ? (V*)ws->r64 : (V*)ws->r32;
+    k_tune_fill<V><<<1024, kBS, 0, s>>>(r, (long)g->n * T, (V)1);
+    st = enqueue_tune_iteration<V>(g, ws, T, nl, tcs, s);     // warm-up
+  }
+  const int reps = 3;
+  if (st == NVD_OK && hipEventRecord(a, s) != hipSuccess) st = NVD_E_DEVICE;
+  for (int i = 0; i < reps && st == NVD_OK; ++i) st = enqueue_tune_iteration<V>(g, ws, T, nl, tcs, s);
+  if (st == NVD_OK && hipEventRecord(b, s) != hipSuccess) st = NVD_E_DEVICE;
+  if (st == NVD_OK && hipEventSynchronize(b) != hipSuccess) st = NVD_E_DEVICE;
+  float t = 0.0f;
+  if (st == NVD_OK && hipEventElapsedTime(&t, a, b) != hipSuccess) st = NVD_E_DEVICE;
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  // leave the vectors zero, as allocated
+  V* vs[4] = {sizeof(V) == 8 ? (V*)ws->x64 : (V*)ws->x32, sizeof(V) == 8 ? (V*)ws->r64 : (V*)ws->r32,
+              sizeof(V) == 8 ? (V*)ws->p64 : (V*)ws->p32, sizeof(V) == 8 ? (V*)ws->q64 : (V*)ws->q32};
+  for (V* v : vs) k_tune_fill<V><<<1024, kBS, 0, s>>>(v, cap, (V)0);
+  if (hipStreamSynchronize(s) != hipSuccess && st == NVD_OK) st = NVD_E_DEVICE;
+  (void)hipFree(tcs);
+  *ms = t / reps;
+  if (st != NVD_OK) set_error("autotuner: iteration timing failed");
+  return st;
+}
+
+nvd_status time_cg_iteration(DevGraph* g, int prec, int T, int nl, hipStream_t s, float* ms) {
+  return prec == 0 ? time_iteration_t<double>(g, T, nl, s, ms) : time_iteration_t<float>(g, T, nl, s, ms);
+}
+
 static nvd_status mean_into(DevGraph* g, Workspace* ws, int T, ProjSrc src, MeanSrc* m,
                             hipStream_t s) {
   *m = MeanSrc{};

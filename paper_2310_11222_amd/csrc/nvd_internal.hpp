@@ -194,8 +194,12 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
 nvd_status project_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
                         double* Dbar, int64_t ldd, double* norms, hipStream_t s);
 int choose_tile(DevGraph* g, int k, int precision, hipStream_t s);
+// One CG iteration (apply + update + direction) on the workspace vectors, timed.
+nvd_status time_cg_iteration(DevGraph* g, int prec, int T, int nl, hipStream_t s, float* ms);
 int tuned_nl(const DevGraph* g, int precision, int T);
 int default_nl(int T);
+// Largest neighbour sub-group count the apply supports for (precision, T).
+int spmm_max_nl(int prec, int T);
 int default_short_grid(int n, int T, int nl);
 
 }  // namespace nvd

@@ -3,18 +3,20 @@
 // row-major, in FP64 or FP32.
 //
 // Work split:
-//  * short rows (<= kLongRow neighbours): a group of G = T*NL lanes per row;
-//    lane (c, j) owns column c and takes neighbours j, j+NL, ...; neighbour
-//    indices are loaded G at a time by the whole group and shuffled out, so
-//    the gathers of x issue back to back; the NL partial sums meet by
-//    cross-lane shuffles.  A wave holds 64/G rows.
+//  * short rows (<= kLongRow neighbours): a group of G = L*NL lanes per row,
+//    where L = T/VW lanes cover one row of X with 16-byte vectors (VW
+//    elements per lane) and NL sub-groups take every NL-th neighbour.  Each
+//    sub-group walks its own row's neighbour list, U neighbours at a time:
+//    the U column indices are loaded first, then the U row gathers, so the
+//    index -> gather dependency is paid once per U neighbours.  A lane group
+//    carries R rows at once.  The NL partial sums meet by cross-lane
+//    shuffles.
 //  * long rows: segments of at most kSeg neighbours, one 256-thread block per
-//    segment (256/T lanes per column), partial sums reduced in LDS; rows with
-//    several segments combine them in fixed order in the last segment block
-//    to arrive (per-row arrival counter), so results do not depend on timing.
-// The CSR and the output are touched once per pass: they are loaded and
-// stored non-temporally so that they do not push the gathered vector out of
-// the last-level cache.
+//    segment, partial sums reduced in LDS; rows with several segments combine
+//    them in fixed order in the last segment block to arrive (per-row arrival
+//    counter), so results do not depend on timing.
+// The CSR and the output are touched once per pass and are loaded and stored
+// non-temporally.
 // Epilogues fuse the consumer of L X:
 //  * EPI_PLAIN: store Y.
 //  * EPI_CG:    q = L p, store q and reduce sigma_c = p_c^T q_c; the grid's
@@ -23,6 +25,12 @@
 //               sum r, sum x per column.
 #include "device_common.hpp"
 #include "prof.hpp"
+
+// Neighbours per unrolled step (U) and rows per lane group (R) of the
+// short-row path; build-time knobs.
+#ifndef NVD_SPMM_U
+#define NVD_SPMM_U 8
+#endif
 
 namespace nvd {
 
@@ -44,76 +52,136 @@ struct SpmmK {
   int nshort_blocks;
 };
 
-template <typename V, bool UNIT, int EPI, int ND>
-__device__ __forceinline__ void spmm_epilogue(const SpmmK<V>& a, int row, int c, V sum, V own,
-                                              V dg, double bb, double (&acc)[ND][1]) {
-  const V yv = dg * own - sum;
-  if constexpr (EPI == EPI_PLAIN) {
-    __builtin_nontemporal_store(yv, &a.y[(long)row * a.ldy + c]);
-  } else if constexpr (EPI == EPI_CG) {
-    __builtin_nontemporal_store(yv, &a.y[(long)row * a.ldy + c]);
-    acc[0][0] += (double)own * (double)yv;
+// VW consecutive elements of a row, loaded and stored as one access.
+template <typename V, int VW>
+struct VecOf {
+  typedef V type __attribute__((ext_vector_type(VW)));
+};
+template <typename V>
+struct VecOf<V, 1> {
+  typedef V type;
+};
+
+template <typename V, int VW>
+__device__ __forceinline__ void unpack(const typename VecOf<V, VW>::type& a, V (&o)[VW]) {
+  if constexpr (VW == 1) {
+    o[0] = a;
   } else {
-    const double rr = bb - (double)yv;
-    __builtin_nontemporal_store((V)rr, &a.y[(long)row * a.ldy + c]);
-    acc[0][0] += bb * (double)own;
-    acc[1][0] += (double)own * rr;
-    acc[2][0] += rr * rr;
-    acc[3][0] += rr;
-    acc[4][0] += (double)own;
+#pragma unroll
+    for (int v = 0; v < VW; ++v) o[v] = a[v];
   }
 }
 
-template <typename V, bool UNIT, int EPI, int ND>
-__device__ __forceinline__ void spmm_epilogue_load(const SpmmK<V>& a, int row, int c, V sum,
-                                                   double (&acc)[ND][1]) {
-  const V own = a.x[(long)row * a.ldx + c];
-  V dg;
-  if constexpr (UNIT)
-    dg = (V)(a.rp[row + 1] - a.rp[row]);
-  else
-    dg = a.deg[row];
-  double bb = 0.0;
-  if constexpr (EPI == EPI_RESID) bb = a.b[(long)row * a.ldb + c];
-  spmm_epilogue<V, UNIT, EPI, ND>(a, row, c, sum, own, dg, bb, acc);
+template <typename V, int VW>
+__device__ __forceinline__ typename VecOf<V, VW>::type pack(const V (&o)[VW]) {
+  typename VecOf<V, VW>::type a;
+  if constexpr (VW == 1) {
+    a = o[0];
+  } else {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) a[v] = o[v];
+  }
+  return a;
 }
 
-// Rows carried at once by one lane group (short-row path).
-template <typename V, int T>
-struct SpmmRows {
-  static constexpr int R = (sizeof(V) == 8 && T >= 32) ? 2 : 4;
+// Elements per lane: 16 bytes when the tile is wide enough and the operands
+// are aligned for it (VEC), else one.
+template <typename V, int T, bool VEC>
+struct SpmmGeom {
+  static constexpr int W16 = 16 / (int)sizeof(V);
+  static constexpr int VW = VEC ? (T < W16 ? T : W16) : 1;
+  static constexpr int L = T / VW;       // lanes per row of X
 };
 
-template <typename V, int T, int NL, bool UNIT, int EPI>
+#ifndef NVD_SPMM_R
+#define NVD_SPMM_R 1
+#endif
+constexpr int kSpmmR = NVD_SPMM_R;
+// Short-row blocks at most (the rest of kMaxBlocks is left to long rows).
+constexpr int kSpmmMaxShortGrid = kMaxBlocks - 1024;
+
+// Epilogue for VW columns c0 .. c0+VW-1 of one row; sum = (A x) entries.
+template <typename V, int VW, bool UNIT, int EPI, int NDA>
+__device__ __forceinline__ void spmm_epilogue(const SpmmK<V>& a, int row, int cv, const V (&sum)[VW],
+                                              const V (&own)[VW], V dg, double (&acc)[NDA][VW]) {
+  using VV = typename VecOf<V, VW>::type;
+  V yv[VW];
+#pragma unroll
+  for (int v = 0; v < VW; ++v) yv[v] = dg * own[v] - sum[v];
+  VV* yp = reinterpret_cast<VV*>(a.y + (long)row * a.ldy) + cv;
+  if constexpr (EPI == EPI_PLAIN) {
+    __builtin_nontemporal_store(pack<V, VW>(yv), yp);
+  } else if constexpr (EPI == EPI_CG) {
+    __builtin_nontemporal_store(pack<V, VW>(yv), yp);
+#pragma unroll
+    for (int v = 0; v < VW; ++v) acc[0][v] += (double)own[v] * (double)yv[v];
+  } else {
+    using BV = typename VecOf<double, VW>::type;
+    double bb[VW];
+    unpack<double, VW>(reinterpret_cast<const BV*>(a.b + (long)row * a.ldb)[cv], bb);
+    V rv[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      const double rr = bb[v] - (double)yv[v];
+      rv[v] = (V)rr;
+      acc[0][v] += bb[v] * (double)own[v];
+      acc[1][v] += (double)own[v] * rr;
+      acc[2][v] += rr * rr;
+      acc[3][v] += rr;
+      acc[4][v] += (double)own[v];
+    }
+    __builtin_nontemporal_store(pack<V, VW>(rv), yp);
+  }
+}
+
+template <typename V, int VW, bool UNIT>
+__device__ __forceinline__ V row_degree(const SpmmK<V>& a, int row) {
+  if constexpr (UNIT)
+    return (V)(a.rp[row + 1] - a.rp[row]);
+  else
+    return a.deg[row];
+}
+
+template <typename V, int T, int NL, bool UNIT, int EPI, bool VEC>
 __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows lr) {
-  constexpr int G = T * NL;
+  using Geo = SpmmGeom<V, T, VEC>;
+  constexpr int VW = Geo::VW;
+  constexpr int L = Geo::L;
+  constexpr int G = L * NL;
   static_assert(G <= 64 && (64 % G) == 0, "lane group must divide a wave");
+  using VV = typename VecOf<V, VW>::type;
   constexpr int RW = 64 / G;
   constexpr int ND = EPI == EPI_CG ? 1 : (EPI == EPI_RESID ? 5 : 0);
   constexpr int NDA = ND > 0 ? ND : 1;
-  __shared__ double sh_long[kBS];
-  __shared__ double sh_red[NDA * kBS];
+  __shared__ double sh_long[kBS * VW];
+  __shared__ double sh_red[ND > 0 ? ND * kBS * VW : 1];
   __shared__ double vals[NDA * kMaxTile];
   __shared__ int s_last;
 
   if constexpr (EPI == EPI_CG) {
     if (a.cs->n_active == 0) return;
   }
-  double acc[NDA][1];
+  double acc[NDA][VW];
 #pragma unroll
-  for (int d = 0; d < NDA; ++d) acc[d][0] = 0.0;
+  for (int d = 0; d < NDA; ++d)
+#pragma unroll
+    for (int v = 0; v < VW; ++v) acc[d][v] = 0.0;
   const int t = threadIdx.x;
+  const VV* X = reinterpret_cast<const VV*>(a.x);
+  const long ldxv = a.ldx / VW;
 
   if ((int)blockIdx.x < a.nlong_blocks) {
     // ---- split-row path: one segment per block, blocks loop over segments
-    constexpr int NJ = kBS / T;
-    const int c = t % T;
-    const int j = t / T;
+    constexpr int NJ = kBS / L;
+    const int cv = t % L;
+    const int j = t / L;
     for (int s = blockIdx.x; s < lr.n_seg; s += a.nlong_blocks) {
       const int row = lr.seg_row[s];
       const int lo = lr.seg_lo[s];
       const int hi = lr.seg_hi[s];
-      V sum = (V)0;
+      V sum[VW];
+#pragma unroll
+      for (int v = 0; v < VW; ++v) sum[v] = (V)0;
       for (int e = lo + j; e < hi; e += NJ) {
         const int col = a.ci[e];
         V wt;
@@ -121,14 +189,25 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
           wt = (V)1;
         else
           wt = a.w[e];
-        sum += wt * a.x[(long)col * a.ldx + c];
+        V xv[VW];
+        unpack<V, VW>(X[(long)col * ldxv + cv], xv);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) sum[v] += wt * xv[v];
       }
-      double part[1][1] = {{(double)sum}};
-      block_reduce_cols<kBS, 1, 1>(part, T, sh_long);
+      double part[1][VW];
+#pragma unroll
+      for (int v = 0; v < VW; ++v) part[0][v] = (double)sum[v];
+      block_reduce_cols<kBS, 1, VW>(part, T, sh_long);   // sh_long[c], c < T: segment sums
       const int first = lr.seg_first[s];
       const int cnt = lr.seg_cnt[s];
       if (cnt == 1) {
-        if (t < T) spmm_epilogue_load<V, UNIT, EPI, NDA>(a, row, t, (V)sh_long[t], acc);
+        if (t < L) {
+          V tot[VW], own[VW];
+#pragma unroll
+          for (int v = 0; v < VW; ++v) tot[v] = (V)sh_long[t * VW + v];
+          unpack<V, VW>(X[(long)row * ldxv + t], own);
+          spmm_epilogue<V, VW, UNIT, EPI, NDA>(a, row, t, tot, own, row_degree<V, VW, UNIT>(a, row), acc);
+        }
       } else {
         if (t < T) st_agent(&lr.seg_part[(long)s * kMaxTile + t], sh_long[t]);
         wait_stores();
@@ -136,10 +215,17 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
         if (t == 0) s_last = (ticket(&lr.row_tick[first]) == (unsigned)(cnt - 1));
         __syncthreads();
         if (s_last) {
-          if (t < T) {
-            double tot = 0.0;
-            for (int i = 0; i < cnt; ++i) tot += ld_agent(&lr.seg_part[(long)(first + i) * kMaxTile + t]);
-            spmm_epilogue_load<V, UNIT, EPI, NDA>(a, row, t, (V)tot, acc);
+          if (t < L) {
+            V tot[VW], own[VW];
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+              double sacc = 0.0;
+              for (int i = 0; i < cnt; ++i)
+                sacc += ld_agent(&lr.seg_part[(long)(first + i) * kMaxTile + t * VW + v]);
+              tot[v] = (V)sacc;
+            }
+            unpack<V, VW>(X[(long)row * ldxv + t], own);
+            spmm_epilogue<V, VW, UNIT, EPI, NDA>(a, row, t, tot, own, row_degree<V, VW, UNIT>(a, row), acc);
           }
           if (t == 0) lr.row_tick[first] = 0u;
         }
@@ -147,112 +233,113 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
       __syncthreads();
     }
   } else {
-    // ---- short rows.  Blocks are renumbered so that each XCD (blocks are
-    // dealt to the 8 XCDs round-robin) walks contiguous row ranges.  Each
-    // lane group carries R rows at once: their row bounds, neighbour indices,
-    // gathers and own values are all issued before any of them is waited on.
+    // ---- short rows.  Consecutive blocks take consecutive row chunks, so
+    // the hardware's round-robin dealing of blocks to the 8 XCDs spreads
+    // every region of the graph over all of them: with preferential
+    // attachment the heavy rows sit together at low ids, and contiguous
+    // per-XCD ranges would leave one XCD with most of the work.
     const int nsb = a.nshort_blocks;
-    int sb = (int)blockIdx.x - a.nlong_blocks;
-    if ((nsb & 7) == 0) sb = (sb & 7) * (nsb >> 3) + (sb >> 3);
+    const int sb = (int)blockIdx.x - a.nlong_blocks;
     const int lane = t & 63;
     const int wave = t >> 6;
     const int g = lane / G;
     const int li = lane % G;
-    const int c = li % T;
-    const int j = li / T;
-    constexpr int R = SpmmRows<V, T>::R;
+    const int cv = li % L;                 // vector index within the row
+    const int j = li / L;                  // neighbour sub-group
+    constexpr int R = kSpmmR;
+    constexpr int U = NVD_SPMM_U;
     constexpr int ROWS_PER_WAVE = RW * R;
     constexpr int ROWS_PER_STEP = (kBS / 64) * ROWS_PER_WAVE;
-    constexpr int MM = G / NL;             // neighbours per lane per chunk (= T)
-    constexpr int MB = MM < 8 ? MM : 8;
     for (int base = sb * ROWS_PER_STEP; base < a.n; base += nsb * ROWS_PER_STEP) {
       int row[R], rs[R], deg[R];
       bool mine[R];
-      V own[R], dg[R];
-      double bb[R];
+      V own[R][VW], dg[R];
+      int mx = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         row[r] = base + wave * ROWS_PER_WAVE + r * RW + g;
         rs[r] = 0;
-        deg[r] = -1;                        // -1: no row in this slot
+        deg[r] = 0;
+        mine[r] = false;
         if (row[r] < a.n) {
           rs[r] = a.rp[row[r]];
-          deg[r] = a.rp[row[r] + 1] - rs[r];
+          const int d = a.rp[row[r] + 1] - rs[r];
+          mine[r] = d <= kLongRow;
+          deg[r] = mine[r] ? d : 0;
         }
+        mx = deg[r] > mx ? deg[r] : mx;
       }
-      int maxdeg = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        mine[r] = deg[r] >= 0 && deg[r] <= kLongRow;
-        own[r] = mine[r] ? a.x[(long)row[r] * a.ldx + c] : (V)0;
+        const int orow = mine[r] ? row[r] : 0;
+        unpack<V, VW>(X[(long)orow * ldxv + cv], own[r]);
         if constexpr (UNIT)
-          dg[r] = (V)(deg[r] > 0 ? deg[r] : 0);
+          dg[r] = (V)deg[r];
         else
           dg[r] = mine[r] ? a.deg[row[r]] : (V)0;
-        bb[r] = 0.0;
-        if constexpr (EPI == EPI_RESID) bb[r] = mine[r] ? a.b[(long)row[r] * a.ldb + c] : 0.0;
-        if (!mine[r]) deg[r] = 0;
-        maxdeg = deg[r] > maxdeg ? deg[r] : maxdeg;
       }
-      V sum[R];
+      V sum[R][VW];
 #pragma unroll
-      for (int r = 0; r < R; ++r) sum[r] = (V)0;
-      for (int off = 0; off < maxdeg; off += G) {          // uniform across the group
-        int myc[R], cnt[R];
-        V myw[R];
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) sum[r][v] = (V)0;
+      for (int e0 = j; e0 < mx; e0 += NL * U) {
+        int col[R][U];
+        V wt[R][U];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          cnt[r] = deg[r] - off;
-          cnt[r] = cnt[r] < 0 ? 0 : (cnt[r] > G ? G : cnt[r]);
-          myc[r] = li < cnt[r] ? __builtin_nontemporal_load(&a.ci[rs[r] + off + li]) : 0;
-          myw[r] = (V)1;
-          if constexpr (!UNIT)
-            myw[r] = li < cnt[r] ? __builtin_nontemporal_load(&a.w[rs[r] + off + li]) : (V)0;
-        }
-        int maxcnt = 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) maxcnt = cnt[r] > maxcnt ? cnt[r] : maxcnt;
-#pragma unroll
-        for (int m0 = 0; m0 < MM; m0 += MB) {
-          if (NL * m0 >= maxcnt) break;                    // uniform across the group
-          V xv[R][MB];
-          V wv[R][MB];
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-#pragma unroll
-            for (int m = 0; m < MB; ++m) {
-              const int idx = j + NL * (m0 + m);
-              const int col = __shfl(myc[r], idx, G);
+          for (int u = 0; u < U; ++u) {
+            // lanes past the end of their row issue no loads
+            const int e = e0 + NL * u;
+            col[r][u] = 0;
+            wt[r][u] = (V)0;
+            if (e < deg[r]) {
+              col[r][u] = __builtin_nontemporal_load(&a.ci[rs[r] + e]);
               if constexpr (UNIT)
-                wv[r][m] = (V)1;
+                wt[r][u] = (V)1;
               else
-                wv[r][m] = __shfl(myw[r], idx, G);
-              xv[r][m] = idx < cnt[r] ? a.x[(long)col * a.ldx + c] : (V)0;
+                wt[r][u] = __builtin_nontemporal_load(&a.w[rs[r] + e]);
             }
           }
-#pragma unroll
-          for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int m = 0; m < MB; ++m) sum[r] += wv[r][m] * xv[r][m];
         }
+        VV xv[R][U];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            xv[r][u] = VV{};
+            if (e0 + NL * u < deg[r]) xv[r][u] = X[(long)col[r][u] * ldxv + cv];
+          }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            V xs[VW];
+            unpack<V, VW>(xv[r][u], xs);
+#pragma unroll
+            for (int v = 0; v < VW; ++v) sum[r][v] += wt[r][u] * xs[v];
+          }
       }
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
+      for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int off = T; off < G; off <<= 1) sum[r] += __shfl_xor(sum[r], off, 64);
-      }
+        for (int v = 0; v < VW; ++v)
+#pragma unroll
+          for (int off = L; off < G; off <<= 1) sum[r][v] += __shfl_xor(sum[r][v], off, 64);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (j == 0 && mine[r]) spmm_epilogue<V, UNIT, EPI, NDA>(a, row[r], c, sum[r], own[r], dg[r], bb[r], acc);
+        if (j == 0 && mine[r])
+          spmm_epilogue<V, VW, UNIT, EPI, NDA>(a, row[r], cv, sum[r], own[r], dg[r], acc);
       }
     }
   }
 
   if constexpr (ND > 0) {
-    block_reduce_cols<kBS, ND, 1>(acc, T, sh_red);
+    block_reduce_cols<kBS, ND, VW>(acc, T, sh_red);
     if (t < T) {
 #pragma unroll
-      for (int d = 0; d < ND; ++d) vals[d * T + t] = sh_red[d * kBS + t];
+      for (int d = 0; d < ND; ++d) vals[d * T + t] = sh_red[d * kBS * VW + t];
     }
     __syncthreads();
     if (!grid_reduce<kBS>(vals, ND * T, red)) return;
@@ -282,71 +369,98 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-template <typename V, int T, int NL, bool UNIT, int EPI>
-static void launch_one(const SpmmK<V>& k, const GridRed& red, const LongRows& lr, int grid,
-                       hipStream_t s) {
-  k_spmm<V, T, NL, UNIT, EPI><<<grid, kBS, 0, s>>>(k, red, lr);
+template <typename V, int T, int NL, bool VEC>
+constexpr bool spmm_fits() {
+  return SpmmGeom<V, T, VEC>::L * NL <= 64;
 }
 
-template <typename V, int T, int NL, int EPI>
-static void launch_unit(bool unit, const SpmmK<V>& k, const GridRed& red, const LongRows& lr,
-                        int grid, hipStream_t s) {
+template <typename V, int T, int NL, bool VEC, int EPI>
+static void launch_geo(bool unit, const SpmmK<V>& k, const GridRed& red, const LongRows& lr,
+                       int grid, hipStream_t s) {
   if (unit)
-    launch_one<V, T, NL, true, EPI>(k, red, lr, grid, s);
+    k_spmm<V, T, NL, true, EPI, VEC><<<grid, kBS, 0, s>>>(k, red, lr);
   else
-    launch_one<V, T, NL, false, EPI>(k, red, lr, grid, s);
+    k_spmm<V, T, NL, false, EPI, VEC><<<grid, kBS, 0, s>>>(k, red, lr);
 }
 
-template <typename V, int T, int EPI>
+// Rows handled per block and step for (T, nl, vec); 0 if the configuration
+// does not exist.
+template <typename V>
+static int rows_per_block(int T, int nl, bool vec) {
+  const int W16 = 16 / (int)sizeof(V);
+  const int VW = vec ? (T < W16 ? T : W16) : 1;
+  const int G = (T / VW) * nl;
+  if (G > 64 || 64 % G) return 0;
+  return (kBS / 64) * (64 / G) * kSpmmR;
+}
+
+template <typename V, int T, int EPI, bool VEC>
 static bool launch_nl(int nl, bool unit, const SpmmK<V>& k, const GridRed& red,
                       const LongRows& lr, int grid, hipStream_t s) {
   switch (nl) {
-    case 1: launch_unit<V, T, 1, EPI>(unit, k, red, lr, grid, s); return true;
+    case 1:
+      if constexpr (spmm_fits<V, T, 1, VEC>()) { launch_geo<V, T, 1, VEC, EPI>(unit, k, red, lr, grid, s); return true; }
+      break;
     case 2:
-      if constexpr (T * 2 <= 64) { launch_unit<V, T, 2, EPI>(unit, k, red, lr, grid, s); return true; }
+      if constexpr (spmm_fits<V, T, 2, VEC>()) { launch_geo<V, T, 2, VEC, EPI>(unit, k, red, lr, grid, s); return true; }
       break;
     case 4:
-      if constexpr (T * 4 <= 64) { launch_unit<V, T, 4, EPI>(unit, k, red, lr, grid, s); return true; }
+      if constexpr (spmm_fits<V, T, 4, VEC>()) { launch_geo<V, T, 4, VEC, EPI>(unit, k, red, lr, grid, s); return true; }
       break;
     case 8:
-      if constexpr (T * 8 <= 64) { launch_unit<V, T, 8, EPI>(unit, k, red, lr, grid, s); return true; }
+      if constexpr (spmm_fits<V, T, 8, VEC>()) { launch_geo<V, T, 8, VEC, EPI>(unit, k, red, lr, grid, s); return true; }
       break;
     default: break;
   }
   return false;
 }
 
-template <typename V, int EPI>
+template <typename V, int EPI, bool VEC>
 static bool launch_t(int T, int nl, bool unit, const SpmmK<V>& k, const GridRed& red,
                      const LongRows& lr, int grid, hipStream_t s) {
   switch (T) {
-    case 1: return launch_nl<V, 1, EPI>(nl, unit, k, red, lr, grid, s);
-    case 2: return launch_nl<V, 2, EPI>(nl, unit, k, red, lr, grid, s);
-    case 4: return launch_nl<V, 4, EPI>(nl, unit, k, red, lr, grid, s);
-    case 8: return launch_nl<V, 8, EPI>(nl, unit, k, red, lr, grid, s);
-    case 16: return launch_nl<V, 16, EPI>(nl, unit, k, red, lr, grid, s);
-    case 32: return launch_nl<V, 32, EPI>(nl, unit, k, red, lr, grid, s);
-    case 64: return launch_nl<V, 64, EPI>(nl, unit, k, red, lr, grid, s);
+    case 1: return launch_nl<V, 1, EPI, VEC>(nl, unit, k, red, lr, grid, s);
+    case 2: return launch_nl<V, 2, EPI, VEC>(nl, unit, k, red, lr, grid, s);
+    case 4: return launch_nl<V, 4, EPI, VEC>(nl, unit, k, red, lr, grid, s);
+    case 8: return launch_nl<V, 8, EPI, VEC>(nl, unit, k, red, lr, grid, s);
+    case 16: return launch_nl<V, 16, EPI, VEC>(nl, unit, k, red, lr, grid, s);
+    case 32: return launch_nl<V, 32, EPI, VEC>(nl, unit, k, red, lr, grid, s);
+    case 64: return launch_nl<V, 64, EPI, VEC>(nl, unit, k, red, lr, grid, s);
     default: return false;
   }
 }
 
-// Default neighbour lanes per row: enough lanes to cover a typical short row
-// while keeping G = T*NL <= 64.
-int default_nl(int T) {
-  if (T >= 16) return 1;
-  if (T == 8) return 2;
-  if (T == 4) return 4;
-  return 8;
+int spmm_max_nl(int prec, int T) {
+  const int elem = prec == 0 ? 8 : 4;
+  const int W16 = 16 / elem;
+  const int VW = T < W16 ? T : W16;
+  int nl = 1;
+  while (nl * 2 <= 8 && (T / VW) * nl * 2 <= 64) nl *= 2;
+  return nl;
 }
 
-int default_short_grid(int n, int T, int nl) {
-  const int rows_per_step = (kBS / 64) * (64 / (T * nl));
+// Default neighbour sub-groups per row: one (a lane group walks the whole
+// neighbour list of its row).
+int default_nl(int T) {
+  (void)T;
+  return 1;
+}
+
+static int short_grid(int n, int rows_per_step) {
   long steps = ((long)n + rows_per_step - 1) / rows_per_step;
-  long grid = steps < 2048 ? steps : 2048;
+  long grid = steps < kSpmmMaxShortGrid ? steps : kSpmmMaxShortGrid;
   if (grid >= 8) grid &= ~7L;
   if (grid < 1) grid = 1;
   return (int)grid;
+}
+
+int default_short_grid(int n, int T, int nl) {
+  return short_grid(n, rows_per_block<float>(T, nl, true) > 0 ? rows_per_block<float>(T, nl, true) : kBS);
+}
+
+// Rows of vw elements can be accessed as one vector: aligned base and stride.
+static bool vec_rows(const void* p, int64_t ld, int elem, int vw) {
+  return vw == 1 || (((uintptr_t)p % (uintptr_t)(vw * elem)) == 0 && (ld % vw) == 0);
 }
 
 template <typename V>
@@ -372,8 +486,19 @@ static nvd_status launch_typed(const SpmmCall& c, const GridRed& red, hipStream_
   k.ldb = c.ldb;
   k.cs = c.cs;
   const int nl = c.nl > 0 ? c.nl : default_nl(c.T);
+  // vector accesses need aligned rows of X, Y (and B)
+  const int W16 = 16 / (int)sizeof(V);
+  const int vw = c.T < W16 ? c.T : W16;
+  bool vec = vec_rows(c.x, c.ldx, sizeof(V), vw) && vec_rows(c.y, c.ldy, sizeof(V), vw);
+  if (c.epi == EPI_RESID) vec = vec && vec_rows(c.b, c.ldb, sizeof(double), vw);
+  const int rpb = rows_per_block<V>(c.T, nl, vec);
+  if (rpb == 0) {
+    set_error("spmm: unsupported tile/lane configuration T=" + std::to_string(c.T) +
+              " nl=" + std::to_string(nl));
+    return NVD_E_UNSUPPORTED;
+  }
   k.nlong_blocks = g->lr.n_seg < 1024 ? g->lr.n_seg : 1024;
-  int sg = c.grid > 0 ? c.grid : default_short_grid(g->n, c.T, nl);
+  int sg = c.grid > 0 ? c.grid : short_grid(g->n, rpb);
   const int cap = kMaxBlocks - k.nlong_blocks;
   if (sg > cap) sg = cap & ~7;
   k.nshort_blocks = sg;
@@ -384,21 +509,27 @@ static nvd_status launch_typed(const SpmmCall& c, const GridRed& red, hipStream_
     const double sw = unit ? 0.0 : sv;
     const double n = g->n;
     const double csr = (4.0 + sw) * g->nnz + 4.0 * (n + 1) + sw * n;
-    const double vec = c.epi == EPI_RESID ? 3.0 * c.T * 8.0 * n : 2.0 * c.T * sv * n;
-    pid = prof_begin(s, sizeof(V) == 8 ? PK_SPMM64 : PK_SPMM32, csr + vec);
+    const double vecb = c.epi == EPI_RESID ? 3.0 * c.T * 8.0 * n : 2.0 * c.T * sv * n;
+    pid = prof_begin(s, sizeof(V) == 8 ? PK_SPMM64 : PK_SPMM32, csr + vecb);
   }
   bool ok = false;
   switch (c.epi) {
-    case EPI_PLAIN: ok = launch_t<V, EPI_PLAIN>(c.T, nl, unit, k, red, g->lr, grid, s); break;
-    case EPI_CG: ok = launch_t<V, EPI_CG>(c.T, nl, unit, k, red, g->lr, grid, s); break;
+    case EPI_PLAIN:
+      ok = vec ? launch_t<V, EPI_PLAIN, true>(c.T, nl, unit, k, red, g->lr, grid, s)
+               : launch_t<V, EPI_PLAIN, false>(c.T, nl, unit, k, red, g->lr, grid, s);
+      break;
+    case EPI_CG:
+      // solver vectors are always aligned
+      ok = vec && launch_t<V, EPI_CG, true>(c.T, nl, unit, k, red, g->lr, grid, s);
+      break;
     case EPI_RESID:
-      if constexpr (sizeof(V) == 8) ok = launch_t<V, EPI_RESID>(c.T, nl, unit, k, red, g->lr, grid, s);
+      if constexpr (sizeof(V) == 8) ok = vec && launch_t<V, EPI_RESID, true>(c.T, nl, unit, k, red, g->lr, grid, s);
       break;
     default: break;
   }
   prof_end(s, pid);
   if (!ok) {
-    set_error("spmm: unsupported tile/lane configuration T=" + std::to_string(c.T) +
+    set_error("spmm: unsupported tile/lane/alignment configuration T=" + std::to_string(c.T) +
               " nl=" + std::to_string(nl));
     return NVD_E_UNSUPPORTED;
   }

@@ -1,12 +1,14 @@
-// Autotuner for the SpMM tile: the number of right-hand-side columns per
-// pass (T) and the neighbour lanes per row (NL).
+// Autotuner for the tile: the number of right-hand-side columns per solve
+// pass (T) and the neighbour lanes per row of the Laplacian apply (NL).
 //
 // Wider tiles read the CSR fewer times and gather longer rows of X per
 // neighbour (fewer, fuller memory transactions); narrower tiles keep the
-// solver's vectors small enough to stay in the last-level cache.  Which wins
-// depends on the graph, so the candidates are timed on the graph itself: the
-// Laplacian apply of each (T, NL) is run on workspace vectors, and the choice
-// minimising the time for all k columns, ceil(k / T) * t(T, NL), is cached in
+// solver's vectors small enough to stay in the last-level cache, which the
+// vector passes of every iteration (update, direction) feel as much as the
+// apply.  Which wins depends on the graph, so the candidates are timed on the
+// graph itself: for each T the apply alone picks NL, then one whole CG
+// iteration (apply, update, direction) with that NL is timed, and the T
+// minimising the time for all k columns, ceil(k / T) * t_iter(T), is cached in
 // the graph handle per (precision, k bucket).
 #include <algorithm>
 #include <cstdlib>
@@ -80,21 +82,28 @@ int choose_tile(DevGraph* g, int k, int precision, hipStream_t s) {
   while (tmax * 2 <= k && tmax * 2 <= kMaxTile) tmax *= 2;
   if (ensure_workspace(g, tmax, prec == 1) != NVD_OK) return heuristic_tile(k);
   double best = 1e30;
-  int bestT = heuristic_tile(k), bestNL = default_nl(bestT);
+  int bestT = heuristic_tile(k);
   for (int T = 8; T <= tmax; T *= 2) {
-    for (int nl = 1; nl <= 8 && T * nl <= 64; nl *= 2) {
+    float best_apply = 1e30f;
+    int nlT = default_nl(T);
+    for (int nl = 1; nl <= spmm_max_nl(prec, T); nl *= 2) {
       float ms = 0.0f;
       if (time_spmm(g, prec, T, nl, s, &ms) != NVD_OK) return heuristic_tile(k);
-      const double total = (double)((k + T - 1) / T) * ms;
-      if (total < best) {
-        best = total;
-        bestT = T;
-        bestNL = nl;
+      if (ms < best_apply) {
+        best_apply = ms;
+        nlT = nl;
       }
+    }
+    g->tuned_nl[p][log2i(T)] = nlT;
+    float it_ms = 0.0f;
+    if (time_cg_iteration(g, prec, T, nlT, s, &it_ms) != NVD_OK) return heuristic_tile(k);
+    const double total = (double)((k + T - 1) / T) * it_ms;
+    if (total < best) {
+      best = total;
+      bestT = T;
     }
   }
   g->tuned_tile[p][kb] = bestT;
-  g->tuned_nl[p][log2i(bestT)] = bestNL;
   return bestT;
 }
 
