@@ -151,6 +151,38 @@ __device__ __forceinline__ void recount_active(ColState* cs, int T) {
   }
 }
 
+// VW consecutive elements of a row, loaded and stored as one access.
+template <typename V, int VW>
+struct VecOf {
+  typedef V type __attribute__((ext_vector_type(VW)));
+};
+template <typename V>
+struct VecOf<V, 1> {
+  typedef V type;
+};
+
+template <typename V, int VW>
+__device__ __forceinline__ void unpack(const typename VecOf<V, VW>::type& a, V (&o)[VW]) {
+  if constexpr (VW == 1) {
+    o[0] = a;
+  } else {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) o[v] = a[v];
+  }
+}
+
+template <typename V, int VW>
+__device__ __forceinline__ typename VecOf<V, VW>::type pack(const V (&o)[VW]) {
+  typename VecOf<V, VW>::type a;
+  if constexpr (VW == 1) {
+    a = o[0];
+  } else {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) a[v] = o[v];
+  }
+  return a;
+}
+
 template <typename V>
 struct Vec16;
 template <>

@@ -52,38 +52,6 @@ struct SpmmK {
   int nshort_blocks;
 };
 
-// VW consecutive elements of a row, loaded and stored as one access.
-template <typename V, int VW>
-struct VecOf {
-  typedef V type __attribute__((ext_vector_type(VW)));
-};
-template <typename V>
-struct VecOf<V, 1> {
-  typedef V type;
-};
-
-template <typename V, int VW>
-__device__ __forceinline__ void unpack(const typename VecOf<V, VW>::type& a, V (&o)[VW]) {
-  if constexpr (VW == 1) {
-    o[0] = a;
-  } else {
-#pragma unroll
-    for (int v = 0; v < VW; ++v) o[v] = a[v];
-  }
-}
-
-template <typename V, int VW>
-__device__ __forceinline__ typename VecOf<V, VW>::type pack(const V (&o)[VW]) {
-  typename VecOf<V, VW>::type a;
-  if constexpr (VW == 1) {
-    a = o[0];
-  } else {
-#pragma unroll
-    for (int v = 0; v < VW; ++v) a[v] = o[v];
-  }
-  return a;
-}
-
 // Elements per lane: 16 bytes when the tile is wide enough and the operands
 // are aligned for it (VEC), else one.
 template <typename V, int T, bool VEC>
