@@ -74,9 +74,10 @@ def load_golden_batch():
 def bench_batched(steps, warmup):
     """512 connected graphs of uneven size (n log-uniform in [1e3, 1e5], half
     Watts-Strogatz k=6 beta=0.1, half Barabasi-Albert m=4, weights
-    uniform[0.5, 2)), 8 pairs each: one persistent launch (captured in a
-    hipGraph) for all 4096 distances, FP32 CG + FP64 refinement to 1e-8;
-    beside it the plain FP64 solver called one graph at a time."""
+    uniform[0.5, 2)), 8 pairs each, FP32 CG + FP64 refinement to 1e-8, all
+    4096 distances per call: the sweep solver (value), the single persistent
+    launch replayed from a hipGraph, and the plain FP64 solver called one
+    graph at a time."""
     import numpy as np
     import torch
     import paper_2310_11222_amd as nvd
@@ -90,16 +91,21 @@ def bench_batched(steps, warmup):
     packed = batch.pack(w.P, w.Q)
     K = int(packed[0].sum())
     out = torch.empty(K, dtype=torch.float64, device="cuda")
-    for _ in range(warmup):
-        batch.distances(None, None, packed=packed, out=out, rtol=w.rtol)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        d, _, info = batch.distances(None, None, packed=packed, out=out, rtol=w.rtol)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    d = d.cpu().numpy()
-    value = K * steps / (t1 - t0)
+    def timed(persistent):
+        for _ in range(warmup):
+            batch.distances(None, None, packed=packed, out=out, rtol=w.rtol, persistent=persistent)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            d, _, info = batch.distances(None, None, packed=packed, out=out, rtol=w.rtol,
+                                         persistent=persistent)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return d.cpu().numpy(), info, t1 - t0
+
+    dp, _, tp = timed(True)
+    d, info, tsw = timed(False)
+    value = K * steps / tsw
     # plain FP64 solver, one graph at a time, same GPU
     t2 = time.perf_counter()
     d64 = []
@@ -110,14 +116,17 @@ def bench_batched(steps, warmup):
     t3 = time.perf_counter()
     d64 = torch.cat(d64).cpu().numpy()
     gold = load_golden_batch()
-    res = {"workload": "batch512_ws_k6_ba_m4_k8", "value": round(value, 1), "unit": "distances/s",
-           "ms_per_step": round((t1 - t0) * 1e3 / steps, 3), "pairs": K,
-           "graph_launch": batch.query(),
+    res = {"workload": "batch512_ws_k6_ba_m4_k8", "solver": "sweep", "value": round(value, 1),
+           "unit": "distances/s", "ms_per_step": round(tsw * 1e3 / steps, 3), "pairs": K,
+           "persistent": {"value": round(K * steps / tp, 1), "unit": "distances/s",
+                          "ms_per_step": round(tp * 1e3 / steps, 3), "graph_launch": batch.query(),
+                          "max_rel_err": None},
            "iters_mean": float(np.mean([i["iters"] for i in info])),
            "fp64_one_graph_at_a_time": {"value": round(K / (t3 - t2), 1), "unit": "distances/s"},
            "max_rel_err": None, "max_rel_err_fp64": None}
     if gold is not None and gold.size == K:
         res["max_rel_err"] = float(np.max(np.abs(d - gold) / gold))
+        res["persistent"]["max_rel_err"] = float(np.max(np.abs(dp - gold) / gold))
         res["max_rel_err_fp64"] = float(np.max(np.abs(d64 - gold) / gold))
     log(f"batched: {res}")
     batch.close()

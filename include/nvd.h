@@ -80,7 +80,9 @@ enum { NVD_FP64 = 0, NVD_MIXED = 1 };
 enum { NVD_DT_F64 = 0, NVD_DT_F32 = 1 };
 /* nvd_opts.flags */
 enum {
-  NVD_WARM_START = 1u  /* X_inout holds a starting guess on entry */
+  NVD_WARM_START = 1u,      /* X_inout holds a starting guess on entry */
+  NVD_BATCH_PERSISTENT = 2u /* nvd_batch_distances: the single persistent
+                               launch instead of the sweep solver */
 };
 
 typedef struct nvd_graph nvd_graph;
@@ -100,7 +102,7 @@ typedef struct nvd_opts {
   int32_t max_refine;  /* MIXED: outer refinement steps; default 30 */
   int32_t tile_k;      /* columns per SpMM pass: 1,2,4,8,16,32,64; 0 = the
                           library's autotuned choice */
-  uint32_t flags;      /* NVD_WARM_START */
+  uint32_t flags;      /* NVD_WARM_START, NVD_BATCH_PERSISTENT */
 } nvd_opts;
 
 typedef struct nvd_pair_info {
@@ -220,8 +222,13 @@ nvd_status nvd_grad_weights(nvd_graph* g, int32_t k, const double* X,
 /* ---- batches of graphs ----------------------------------------------------
  * nvd_batch_create packs G graphs into one device structure (the graphs may
  * be destroyed afterwards).  nvd_batch_distances solves k_g pairs on every
- * graph g in one persistent launch: FP32 CG with FP64 iterative refinement
- * (opts->precision NVD_MIXED, the default for batches) or FP64 CG.
+ * graph g: FP32 CG with FP64 iterative refinement (opts->precision
+ * NVD_MIXED, the default for batches) or FP64 CG.  Two solvers:
+ *  - sweep (default): the graphs form one block-diagonal operator; every
+ *    phase is one kernel over the rows of all graphs still open, each graph
+ *    and pair keeping its own CG scalars (a few launches per iteration).
+ *  - persistent (opts->flags & NVD_BATCH_PERSISTENT): one cooperative
+ *    launch in which blocks or teams of blocks take graphs from a work plan.
  * k_per_graph: host int32 [G] (each 1..64).
  * P, Q: device float64, graph-major packed: graph g's block is n_g x k_g
  *   row-major (leading dimension k_g) starting at element offset
@@ -229,9 +236,9 @@ nvd_status nvd_grad_weights(nvd_graph* g, int32_t k, const double* X,
  * d_out: device float64 [sum k_g] (graph-major).  X_out: NULL or device
  *   float64 packed like P.  info: NULL or host [sum k_g].
  * Graphs must be connected (NVD_E_UNSUPPORTED at create time otherwise).
- * The launch is captured in a hipGraph and replayed by later calls with the
- * same pointers, pair counts and options (NVD_BATCH_GRAPH=0 launches
- * directly).  Synchronous with respect to `stream`. */
+ * The persistent launch is captured in a hipGraph and replayed by later
+ * calls with the same pointers, pair counts and options (NVD_BATCH_GRAPH=0
+ * launches directly).  Synchronous with respect to `stream`. */
 nvd_status nvd_batch_create(int32_t G, nvd_graph* const* graphs, void* stream,
                             nvd_batch** out);
 nvd_status nvd_batch_destroy(nvd_batch* b);

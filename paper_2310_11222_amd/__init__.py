@@ -239,9 +239,12 @@ class Batch:
         return ks, Pf, Qf
 
     def distances(self, P_list, Q_list, precision="mixed", rtol=1e-8, inner_rtol=1e-5,
-                  max_iter=20000, max_refine=30, return_x=False, packed=None, out=None):
+                  max_iter=20000, max_refine=30, return_x=False, packed=None, out=None,
+                  persistent=False):
         """packed = (ks, Pf, Qf) from Batch.pack reuses device buffers (and so
-        the captured launch); out = preallocated d tensor."""
+        the persistent solver's captured launch); out = preallocated d tensor;
+        persistent = the single persistent launch instead of the sweep
+        solver."""
         torch = _torch()
         if packed is None:
             ks, Pf, Qf = self.pack(P_list, Q_list)
@@ -252,6 +255,8 @@ class Batch:
         X = torch.empty_like(Pf) if return_x else None
         info = (PairInfo * K)()
         o = opts(precision, rtol, inner_rtol, max_iter, max_refine)
+        if persistent:
+            o.flags |= _abi.NVD_BATCH_PERSISTENT
         st = load().nvd_batch_distances(self._h, ks.ctypes.data_as(C.c_void_p), _ptr(Pf),
                                         _ptr(Qf), C.byref(o), _ptr(d), _ptr(X), info,
                                         _stream())

@@ -13,6 +13,7 @@ NVD_OK, NVD_E_ARG, NVD_E_GRAPH, NVD_E_VALUE, NVD_E_NOCONV, NVD_E_BREAKDOWN, \
 NVD_FP64, NVD_MIXED = 0, 1
 NVD_DT_F64, NVD_DT_F32 = 0, 1
 NVD_WARM_START = 1
+NVD_BATCH_PERSISTENT = 2
 
 
 class NvdOpts(C.Structure):

@@ -28,6 +28,7 @@
 #include <numeric>
 #include <vector>
 
+#include "batch_internal.hpp"
 #include "device_common.hpp"
 
 namespace nvd {
@@ -825,83 +826,6 @@ struct BatchPlan {
 
 using namespace nvd;
 
-struct nvd_batch {
-  int G = 0;
-  std::vector<int> n, nnz, weighted;
-  std::vector<long> rp_off, nnz_off, node_off;
-  std::vector<int> long_off, n_long;
-  long tot_n = 0, tot_rp = 0, tot_nnz = 0, tot_long = 0;
-  bool any_weighted = false;
-  // device graph data
-  int* rp = nullptr;
-  int* ci = nullptr;
-  double* w64 = nullptr;
-  float* w32 = nullptr;
-  double* deg64 = nullptr;
-  float* deg32 = nullptr;
-  double* invd64 = nullptr;
-  float* invd32 = nullptr;
-  int* long_rows = nullptr;
-  // workspace (grown on demand)
-  int cap_T = 0;
-  double *b64 = nullptr, *x64 = nullptr, *r64 = nullptr;
-  void *cv = nullptr, *rv = nullptr, *pv = nullptr, *qv = nullptr;
-  int cap_vsize = 0;   // element size of cv..qv
-  BGraph* gd = nullptr;
-  int* plan_buf = nullptr;
-  int plan_cap = 0;
-  unsigned* ctr = nullptr;
-  unsigned* pool_next = nullptr;
-  int* err = nullptr;
-  int* h_err = nullptr;
-  double* part = nullptr;
-  nvd_pair_info* info = nullptr;
-  int info_cap = 0;
-  int64_t bytes = 0;
-  // captured launch (reset + persistent kernel), replayed while the call's
-  // arguments are unchanged
-  hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  std::vector<long> key;
-  bool capture_failed = false;
-  int64_t replays = 0;
-  int64_t captures = 0;
-  int64_t eager = 0;
-  // CG iterations per graph measured on the previous call (work plan weights)
-  std::vector<double> it_est;
-  // optional per-graph timing of the last call (NVD_BATCH_TRACE=1)
-  unsigned long long* trace = nullptr;
-  std::vector<int> last_team_size;
-};
-
-static void batch_drop_graph(nvd_batch* b) {
-  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->gexec = nullptr;
-  b->graph = nullptr;
-  b->key.clear();
-}
-
-static void batch_free(nvd_batch* b) {
-  batch_drop_graph(b);
-  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  void* ptrs[] = {b->rp, b->ci, b->w64, b->w32, b->deg64, b->deg32, b->invd64, b->invd32,
-                  b->long_rows, b->b64, b->x64, b->r64, b->cv, b->rv, b->pv, b->qv, b->gd,
-                  b->plan_buf, b->ctr, b->pool_next, b->err, b->part, b->info, b->trace};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  if (b->h_err) (void)hipHostFree(b->h_err);
-}
-
-template <typename T>
-static nvd_status balloc(nvd_batch* b, T** p, size_t count) {
-  if (count == 0) count = 1;
-  NVD_HIP(hipMalloc((void**)p, count * sizeof(T)));
-  b->bytes += (int64_t)(count * sizeof(T));
-  return NVD_OK;
-}
-
 extern "C" {
 
 nvd_status nvd_batch_create(int32_t G, nvd_graph* const* graphs, void* stream, nvd_batch** out) {
@@ -990,6 +914,7 @@ nvd_status nvd_batch_create(int32_t G, nvd_graph* const* graphs, void* stream, n
     for (int r = 0; r < g->n; ++r)
       if (g->h_rp[r + 1] - g->h_rp[r] > kLongRow) lrows.push_back(r);
   }
+  b->h_long_rows = lrows;
   if (st == NVD_OK && !lrows.empty() &&
       hipMemcpyAsync(b->long_rows, lrows.data(), sizeof(int) * lrows.size(), hipMemcpyHostToDevice, s) != hipSuccess)
     st = NVD_E_DEVICE;
@@ -1356,6 +1281,10 @@ extern "C" nvd_status nvd_batch_distances(nvd_batch* b, const int32_t* k_per_gra
   std::vector<nvd_pair_info> hinfo(K);
   nvd_status st = NVD_E_UNSUPPORTED;
   const bool mixed = o.precision == NVD_MIXED;
+  if (!(o.flags & NVD_BATCH_PERSISTENT)) {
+    st = run_sweep(b, ks, T, o, P, Q, d_out, X_out, hinfo.data(), s);
+    T = 0;    // skip the persistent solver below
+  }
 #define NVD_BT(TT)                                                                          \
   case TT:                                                                                  \
     st = mixed ? run_batch<TT, float>(b, ks, P, Q, o, d_out, X_out, hinfo.data(), s)        \
@@ -1363,7 +1292,7 @@ extern "C" nvd_status nvd_batch_distances(nvd_batch* b, const int32_t* k_per_gra
     break;
   switch (T) {
     NVD_BT(1) NVD_BT(2) NVD_BT(4) NVD_BT(8) NVD_BT(16) NVD_BT(32) NVD_BT(64)
-    default: break;
+    default: break;   // T == 0: solved by the sweep
   }
 #undef NVD_BT
   if (st != NVD_OK) return st;

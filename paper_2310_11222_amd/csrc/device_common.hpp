@@ -51,13 +51,14 @@ __device__ __forceinline__ unsigned ticket(unsigned* p) {
   return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sum `count` rows (row stride kRedStride) of ndt values from src into
+// Sum `count` rows (row stride `stride`) of ndt values from src into
 // dst[ndt] in a fixed order that does not depend on timing: thread t takes
 // entry i = t % ndt of rows s, s + ns, ... (s = t / ndt, ns slices), then the
 // slices are added in slice order.  Loads are agent-scope (coherent) loads.
 template <int BS>
 __device__ __forceinline__ void sum_rows_fixed(const double* src, int count, int ndt,
-                                               double* red /* LDS [BS] */, double* dst) {
+                                               double* red /* LDS [BS] */, double* dst,
+                                               size_t stride = kRedStride) {
   const int t = threadIdx.x;
   if (ndt * 2 <= BS) {
     int ns = BS / ndt;
@@ -68,12 +69,12 @@ __device__ __forceinline__ void sum_rows_fixed(const double* src, int count, int
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       int j = s;
       for (; j + 3 * ns < count; j += 4 * ns) {
-        a0 += ld_agent(src + (size_t)j * kRedStride + i);
-        a1 += ld_agent(src + (size_t)(j + ns) * kRedStride + i);
-        a2 += ld_agent(src + (size_t)(j + 2 * ns) * kRedStride + i);
-        a3 += ld_agent(src + (size_t)(j + 3 * ns) * kRedStride + i);
+        a0 += ld_agent(src + (size_t)j * stride + i);
+        a1 += ld_agent(src + (size_t)(j + ns) * stride + i);
+        a2 += ld_agent(src + (size_t)(j + 2 * ns) * stride + i);
+        a3 += ld_agent(src + (size_t)(j + 3 * ns) * stride + i);
       }
-      for (; j < count; j += ns) a0 += ld_agent(src + (size_t)j * kRedStride + i);
+      for (; j < count; j += ns) a0 += ld_agent(src + (size_t)j * stride + i);
       red[s * ndt + i] = (a0 + a1) + (a2 + a3);
     }
     __syncthreads();
@@ -88,12 +89,12 @@ __device__ __forceinline__ void sum_rows_fixed(const double* src, int count, int
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       int j = 0;
       for (; j + 3 < count; j += 4) {
-        a0 += ld_agent(src + (size_t)j * kRedStride + i);
-        a1 += ld_agent(src + (size_t)(j + 1) * kRedStride + i);
-        a2 += ld_agent(src + (size_t)(j + 2) * kRedStride + i);
-        a3 += ld_agent(src + (size_t)(j + 3) * kRedStride + i);
+        a0 += ld_agent(src + (size_t)j * stride + i);
+        a1 += ld_agent(src + (size_t)(j + 1) * stride + i);
+        a2 += ld_agent(src + (size_t)(j + 2) * stride + i);
+        a3 += ld_agent(src + (size_t)(j + 3) * stride + i);
       }
-      for (; j < count; ++j) a0 += ld_agent(src + (size_t)j * kRedStride + i);
+      for (; j < count; ++j) a0 += ld_agent(src + (size_t)j * stride + i);
       dst[i] = (a0 + a1) + (a2 + a3);
     }
     __syncthreads();

@@ -1,6 +1,7 @@
-"""GPU parity of the batched persistent solver (many uneven graphs in one
-launch) against the CPU oracle, and against the same pairs solved one graph
-at a time."""
+"""GPU parity of the batched solvers (many uneven graphs per call: the sweep
+solver over the block-diagonal operator, and the single persistent launch)
+against the CPU oracle, and against the same pairs solved one graph at a
+time."""
 import numpy as np
 import pytest
 
@@ -44,14 +45,18 @@ def _run(graphs, Ps, Qs, precision, **kw):
     return d.cpu().numpy(), X, info, dgs
 
 
+SOLVERS = [pytest.param(False, id="sweep"), pytest.param(True, id="persistent")]
+
+
+@pytest.mark.parametrize("persistent", SOLVERS)
 @pytest.mark.parametrize("precision,tol", [("mixed", 1e-6), ("fp64", 1e-8)])
-def test_small_batch_matches_oracle(precision, tol):
+def test_small_batch_matches_oracle(precision, tol, persistent):
     sizes = [300, 1200, 3500, 800, 2000, 450, 3000, 900, 1500, 600]
     ks = [8] * len(sizes)
     graphs, Ps, Qs = _mk_batch(1, sizes, ks)
-    say("batch small", precision)
+    say("batch small", precision, "persistent" if persistent else "sweep")
     d, X, info, _ = _run(graphs, Ps, Qs, precision, rtol=1e-10 if precision == "fp64" else 1e-8,
-                         return_x=True)
+                         return_x=True, persistent=persistent)
     off = 0
     xoff = 0
     for g, P, Q in zip(graphs, Ps, Qs):
@@ -66,12 +71,13 @@ def test_small_batch_matches_oracle(precision, tol):
     assert all(i["status"] == 0 for i in info)
 
 
-def test_uneven_k_and_equivalence_with_single_solves():
+@pytest.mark.parametrize("persistent", SOLVERS)
+def test_uneven_k_and_equivalence_with_single_solves(persistent):
     sizes = [700, 1600, 400, 2500, 1000]
     ks = [1, 8, 3, 5, 2]
     graphs, Ps, Qs = _mk_batch(2, sizes, ks)
-    say("batch uneven k")
-    d, _, info, dgs = _run(graphs, Ps, Qs, "mixed", rtol=1e-8)
+    say("batch uneven k", "persistent" if persistent else "sweep")
+    d, _, info, dgs = _run(graphs, Ps, Qs, "mixed", rtol=1e-8, persistent=persistent)
     off = 0
     for dg, g, P, Q in zip(dgs, graphs, Ps, Qs):
         single, _, _ = dg.distances(P, Q, precision="mixed", rtol=1e-8)
@@ -82,15 +88,18 @@ def test_uneven_k_and_equivalence_with_single_solves():
         off += P.shape[1]
 
 
+@pytest.mark.parametrize("persistent", SOLVERS)
 @pytest.mark.parametrize("precision,tol", [("mixed", 1e-6), ("fp64", 1e-8)])
-def test_team_path_large_graph_among_small(precision, tol):
-    """One graph far above a block's share of the work gets a multi-block
-    team (barriers, coherent shared vectors); the rest go to the pool."""
+def test_team_path_large_graph_among_small(precision, tol, persistent):
+    """One graph far above a block's share of the work: in the persistent
+    solver it gets a multi-block team (barriers, coherent shared vectors) and
+    the rest go to the pool; in the sweep it is just more chunks."""
     sizes = [60000] + [400] * 30
     ks = [8] * len(sizes)
     graphs, Ps, Qs = _mk_batch(3, sizes, ks)
-    say("batch team", precision)
-    d, _, info, _ = _run(graphs, Ps, Qs, precision, rtol=1e-10 if precision == "fp64" else 1e-8)
+    say("batch team", precision, "persistent" if persistent else "sweep")
+    d, _, info, _ = _run(graphs, Ps, Qs, precision, rtol=1e-10 if precision == "fp64" else 1e-8,
+                         persistent=persistent)
     ref0 = oracle.ge_pcg(graphs[0].n, graphs[0].row_ptr, graphs[0].col_idx, graphs[0].w,
                          Ps[0], Qs[0])["d"]
     assert rel_err(d[:8], ref0).max() <= tol
@@ -100,11 +109,12 @@ def test_team_path_large_graph_among_small(precision, tol):
         off += 8
 
 
-def test_workload_shape_reduced_scale():
+@pytest.mark.parametrize("persistent", SOLVERS)
+def test_workload_shape_reduced_scale(persistent):
     """The 512-graph workload's recipe at 1/10 of the node counts, 64 graphs."""
     w = workload(3, scale=0.1, num_graphs=64)
-    say("batch c3 reduced", sum(g.n for g in w.graphs))
-    d, _, info, _ = _run(w.graphs, w.P, w.Q, "mixed", rtol=1e-8)
+    say("batch c3 reduced", sum(g.n for g in w.graphs), "persistent" if persistent else "sweep")
+    d, _, info, _ = _run(w.graphs, w.P, w.Q, "mixed", rtol=1e-8, persistent=persistent)
     off = 0
     worst = 0.0
     for g, P, Q in zip(w.graphs, w.P, w.Q):
@@ -124,7 +134,7 @@ def test_batch_rejects_disconnected_graph():
 
 
 def test_graph_capture_replays_match_eager():
-    """The batched launch is captured once and replayed; every replay (with
+    """The persistent launch is captured once and replayed; every replay (with
     the program's own eager GPU work and synchronisations in between) must
     reproduce the direct-launch result bit for bit."""
     import os
@@ -142,14 +152,14 @@ def test_graph_capture_replays_match_eager():
     try:
         # the first call measures per-graph iteration counts, which set the
         # work plan (team sizes, hence summation order) of the calls after it
-        batch.distances(None, None, packed=packed)
-        eager = batch.distances(None, None, packed=packed)[0].cpu().numpy()
+        batch.distances(None, None, packed=packed, persistent=True)
+        eager = batch.distances(None, None, packed=packed, persistent=True)[0].cpu().numpy()
     finally:
         del os.environ["NVD_BATCH_GRAPH"]
     out = torch.empty(K, dtype=torch.float64, device="cuda")
     for rep in range(4):
         out.fill_(-1.0)
-        d = batch.distances(None, None, packed=packed, out=out)[0].cpu().numpy()
+        d = batch.distances(None, None, packed=packed, out=out, persistent=True)[0].cpu().numpy()
         assert np.array_equal(d, eager), (rep, np.abs(d - eager).max())
         # unrelated eager work between replays
         dgs[1].distances(Ps[1], Qs[1], precision="fp64")
@@ -158,3 +168,36 @@ def test_graph_capture_replays_match_eager():
     print("[batch-graph]", q, flush=True)
     assert q["eager"] == 2
     assert q["captures"] == 1 and q["replays"] == 3, q
+
+
+def test_sweep_repeatable_and_close_to_persistent():
+    """The sweep sums every graph's chunk partials in chunk order: two calls
+    agree bit for bit; it agrees with the persistent solver to the mixed
+    tolerance and with the oracle, and returns mean-zero x per graph.  The
+    40000-node BA graph has hubs above 128 neighbours (chunks of one row
+    applied by a whole block)."""
+    sizes = [5000, 300, 12000, 800, 2500, 40000, 1000]
+    ks = [8, 4, 8, 1, 8, 8, 2]
+    graphs, Ps, Qs = _mk_batch(7, sizes, ks)
+    assert np.diff(graphs[5].row_ptr).max() > 128
+    import paper_2310_11222_amd as nvd
+    say("batch sweep repeat")
+    batch = nvd.Batch([dev_graph(g) for g in graphs])
+    packed = batch.pack(Ps, Qs)
+    d1, X1, _ = batch.distances(None, None, packed=packed, return_x=True)
+    d2, X2, _ = batch.distances(None, None, packed=packed, return_x=True)
+    assert np.array_equal(d1.cpu().numpy(), d2.cpu().numpy())
+    assert np.array_equal(X1.cpu().numpy(), X2.cpu().numpy())
+    dp, _, _ = batch.distances(None, None, packed=packed, persistent=True)
+    assert rel_err(d1.cpu().numpy(), dp.cpu().numpy()).max() <= 2e-6
+    off = 0
+    for g, P, Q in zip(graphs, Ps, Qs):
+        k = P.shape[1]
+        assert rel_err(d1.cpu().numpy()[off:off + k], _oracle(g, P, Q)).max() <= 1e-6
+        off += k
+    X = X1.cpu().numpy()
+    off = 0
+    for g, k in zip(graphs, ks):
+        xg = X[off:off + g.n * k].reshape(g.n, k)
+        assert np.abs(xg.sum(axis=0)).max() <= 1e-9 * np.abs(xg).sum()
+        off += g.n * k

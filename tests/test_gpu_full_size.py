@@ -42,21 +42,32 @@ def test_ba_1e6_all_64_pairs(precision, tol):
 
 
 def test_batch_512_graphs_all_4096_pairs():
+    """Both batched solvers at full size; the persistent one twice (direct or
+    captured launch, then a replay), the sweep twice (bit-identical)."""
     import torch
     import paper_2310_11222_amd as nvd
     ref, meta = _golden("c3")
     w = workload(3)
     assert len(w.graphs) == meta["graphs"] and sum(g.n for g in w.graphs) == meta["n_total"]
-    say("full c3 batch", meta["n_total"])
     dgs = [nvd.Graph(g.row_ptr, g.col_idx, g.w) for g in w.graphs]
     batch = nvd.Batch(dgs)
     packed = batch.pack(w.P, w.Q)
     out = torch.empty(int(packed[0].sum()), dtype=torch.float64, device="cuda")
-    for rep in range(2):               # direct or captured launch, then a replay
-        d, _, info = batch.distances(None, None, packed=packed, out=out, rtol=w.rtol)
-        e = rel_err(d.cpu().numpy(), ref)
-        assert e.max() <= 1e-6, (rep, e.max())
-        assert all(i["status"] == 0 for i in info)
+    for persistent in (False, True):
+        say("full c3 batch", meta["n_total"], "persistent" if persistent else "sweep")
+        first = None
+        for rep in range(2):
+            d, _, info = batch.distances(None, None, packed=packed, out=out, rtol=w.rtol,
+                                         persistent=persistent)
+            d = d.cpu().numpy()
+            e = rel_err(d, ref)
+            assert e.max() <= 1e-6, (persistent, rep, e.max())
+            assert all(i["status"] == 0 for i in info)
+            if not persistent:
+                if first is None:
+                    first = d.copy()
+                else:
+                    assert np.array_equal(d, first)
 
 
 def test_configuration_model_1e7_16_pairs():
