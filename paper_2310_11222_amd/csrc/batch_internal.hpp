@@ -64,6 +64,8 @@ struct nvd_batch {
   int n_chunks = 0;
   int* ch_buf = nullptr;               // [3][n_chunks]: graph, first row, end row (-1: one long row)
   std::vector<int> ch_first, ch_nshort, ch_nlong;   // per graph
+  std::vector<int> ch_xcd;             // XCD of each graph in the current table
+  int xfirst[8] = {}, xcount[8] = {};  // chunk range of each XCD
   void* sg_dev = nullptr;              // per-graph descriptors of the sweep kernels
   double* spart = nullptr;             // per-chunk partial sums
   size_t spart_cap = 0;

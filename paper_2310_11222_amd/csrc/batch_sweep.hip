@@ -27,7 +27,10 @@
 namespace nvd {
 
 constexpr int SBS = 256;          // threads per block of the sweep kernels
-constexpr int kChunkRows = 512;   // rows per short chunk
+#ifndef NVD_CHUNK_ROWS
+#define NVD_CHUNK_ROWS 1024
+#endif
+constexpr int kChunkRows = NVD_CHUNK_ROWS;   // rows per short chunk
 constexpr int kSweepGrid = 2048;  // blocks per sweep kernel at most
 
 struct SGraph {
@@ -47,6 +50,7 @@ struct SState {
 
 struct SArgs {
   int G, T, n_chunks, pstride;
+  int xfirst[8], xcount[8];   // chunk range of each XCD's graphs
   const SGraph* sg;
   const int* ch_graph;
   const int* ch_lo;
@@ -76,6 +80,16 @@ struct SArgs {
   double rtol2, irtol2;
   int max_iter, max_refine;
 };
+
+// Chunk loop of a sweep kernel.  Blocks are dealt to the 8 XCDs round-robin
+// (block b runs on XCD b % 8), and every graph's chunks sit in one XCD's
+// range, so a graph is swept by the blocks of one XCD at about the same time
+// and its gathered vector stays in that XCD's L2.  (Where blocks land
+// elsewhere only speed changes: each chunk is still processed exactly once.)
+#define SWEEP_CHUNKS(a, ch)                                                            \
+  for (int sweep_j = (int)(blockIdx.x >> 3), sweep_x = (int)(blockIdx.x & 7), ch = 0; \
+       sweep_j < (a).xcount[sweep_x] && ((ch = (a).xfirst[sweep_x] + sweep_j), true); \
+       sweep_j += (int)(gridDim.x >> 3))
 
 // ---------------------------------------------------------------------------
 // chunk reductions
@@ -182,7 +196,7 @@ __global__ __launch_bounds__(SBS) void ks_delta(SArgs a) {
   __shared__ double red[SBS];
   const int t = threadIdx.x;
   const int c = t % T;
-  for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
+  SWEEP_CHUNKS(a, ch) {
     const int hi = a.ch_hi[ch];
     if (hi < 0) continue;
     const int g = a.ch_graph[ch];
@@ -214,7 +228,7 @@ __global__ __launch_bounds__(SBS) void ks_proj(SArgs a) {
   __shared__ double red[SBS];
   const int t = threadIdx.x;
   const int c = t % T;
-  for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
+  SWEEP_CHUNKS(a, ch) {
     const int hi = a.ch_hi[ch];
     if (hi < 0) continue;
     const int g = a.ch_graph[ch];
@@ -282,7 +296,7 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
     xall = reinterpret_cast<const V*>(a.x64);
     yall = reinterpret_cast<V*>(a.r64);
   }
-  for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
+  SWEEP_CHUNKS(a, ch) {
     const int g = a.ch_graph[ch];
     if constexpr (EPI == EPI_CG) {
       if (!a.s.g_act[g]) continue;
@@ -368,8 +382,8 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
             col[u] = 0;
             wt[u] = (V)0;
             if (e0 + u < deg) {
-              col[u] = __builtin_nontemporal_load(&ci[rs + e0 + u]);
-              wt[u] = unit ? (V)1 : __builtin_nontemporal_load(&wv[rs + e0 + u]);
+              col[u] = NVD_CSR_LOAD(&ci[rs + e0 + u]);
+              wt[u] = unit ? (V)1 : NVD_CSR_LOAD(&wv[rs + e0 + u]);
             }
           }
           VV xv[U];
@@ -488,7 +502,7 @@ __global__ __launch_bounds__(SBS) void ks_inner_init(SArgs a, int first_step) {
   const int t = threadIdx.x;
   const int c = t % T;
   const V* invd_all = invd_ptr<V>(a);
-  for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
+  SWEEP_CHUNKS(a, ch) {
     const int hi = a.ch_hi[ch];
     if (hi < 0) continue;
     const int g = a.ch_graph[ch];
@@ -545,7 +559,7 @@ __global__ __launch_bounds__(SBS) void ks_update(SArgs a) {
   __shared__ double red[SBS];
   const int t = threadIdx.x;
   const V* invd_all = invd_ptr<V>(a);
-  for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
+  SWEEP_CHUNKS(a, ch) {
     const int hi = a.ch_hi[ch];
     if (hi < 0) continue;
     const int g = a.ch_graph[ch];
@@ -620,7 +634,7 @@ __global__ __launch_bounds__(SBS) void ks_direction(SArgs a) {
   using VT = typename SV::type;
   const int t = threadIdx.x;
   const V* invd_all = invd_ptr<V>(a);
-  for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
+  SWEEP_CHUNKS(a, ch) {
     const int hi = a.ch_hi[ch];
     if (hi < 0) continue;
     const int g = a.ch_graph[ch];
@@ -651,7 +665,7 @@ template <typename V, int T>
 __global__ __launch_bounds__(SBS) void ks_accum(SArgs a) {
   const int t = threadIdx.x;
   const int c = t % T;
-  for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
+  SWEEP_CHUNKS(a, ch) {
     const int hi = a.ch_hi[ch];
     if (hi < 0) continue;
     const int g = a.ch_graph[ch];
@@ -673,7 +687,7 @@ __global__ __launch_bounds__(SBS) void ks_xmean(SArgs a) {
   __shared__ double vals[kMaxTile];
   __shared__ double red[SBS];
   const int t = threadIdx.x;
-  for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
+  SWEEP_CHUNKS(a, ch) {
     const int hi = a.ch_hi[ch];
     if (hi < 0) continue;
     const int g = a.ch_graph[ch];
@@ -694,7 +708,7 @@ template <int T>
 __global__ __launch_bounds__(SBS) void ks_xsub(SArgs a) {
   const int t = threadIdx.x;
   const int c = t % T;
-  for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
+  SWEEP_CHUNKS(a, ch) {
     const int hi = a.ch_hi[ch];
     if (hi < 0) continue;
     const int g = a.ch_graph[ch];
@@ -711,7 +725,7 @@ template <int T>
 __global__ __launch_bounds__(SBS) void ks_xout(SArgs a) {
   const int t = threadIdx.x;
   const int c = t % T;
-  for (int ch = blockIdx.x; ch < a.n_chunks; ch += gridDim.x) {
+  SWEEP_CHUNKS(a, ch) {
     const int hi = a.ch_hi[ch];
     if (hi < 0) continue;
     const int g = a.ch_graph[ch];
@@ -729,37 +743,71 @@ __global__ __launch_bounds__(SBS) void ks_xout(SArgs a) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// Graphs are dealt to the 8 XCDs so that every XCD gets about the same
+// rows + nonzeros from each class of iteration counts (graphs in decreasing
+// order of the iterations measured on the previous call, then of size, each
+// to the least-loaded XCD): the open work stays balanced as graphs converge.
+// The chunk table lists each XCD's graphs in turn; it is rebuilt when the
+// assignment changes.  Results do not depend on it: a graph's chunks and
+// their summation order are fixed by its rows alone.
 static nvd_status build_chunks(nvd_batch* b, hipStream_t s) {
-  if (b->ch_buf) return NVD_OK;
-  std::vector<int> cg, clo, chi;
-  b->ch_first.assign(b->G, 0);
-  b->ch_nshort.assign(b->G, 0);
-  b->ch_nlong.assign(b->G, 0);
-  for (int g = 0; g < b->G; ++g) {
-    b->ch_first[g] = (int)cg.size();
-    const int n = b->n[g];
-    for (int lo = 0; lo < n; lo += kChunkRows) {
-      cg.push_back(g);
-      clo.push_back(lo);
-      chi.push_back(std::min(n, lo + kChunkRows));
-    }
-    b->ch_nshort[g] = (int)cg.size() - b->ch_first[g];
-    for (int q = 0; q < b->n_long[g]; ++q) {
-      cg.push_back(g);
-      clo.push_back(b->h_long_rows[b->long_off[g] + q]);
-      chi.push_back(-1);
-    }
-    b->ch_nlong[g] = b->n_long[g];
+  const int G = b->G;
+  std::vector<int> order(G);
+  for (int g = 0; g < G; ++g) order[g] = g;
+  auto size_of = [&](int g) { return (double)b->nnz[g] + 3.0 * b->n[g]; };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (b->it_est[x] != b->it_est[y]) return b->it_est[x] > b->it_est[y];
+    return size_of(x) > size_of(y);
+  });
+  std::vector<int> xcd(G, 0);
+  double load[8] = {};
+  for (int g : order) {
+    int best = 0;
+    for (int q = 1; q < 8; ++q)
+      if (load[q] < load[best]) best = q;
+    xcd[g] = best;
+    load[best] += size_of(g);
   }
-  b->n_chunks = (int)cg.size();
+  if (b->ch_buf && xcd == b->ch_xcd) return NVD_OK;
+  std::vector<int> cg, clo, chi;
+  b->ch_first.assign(G, 0);
+  b->ch_nshort.assign(G, 0);
+  b->ch_nlong.assign(G, 0);
+  for (int q = 0; q < 8; ++q) {
+    b->xfirst[q] = (int)cg.size();
+    for (int g : order) {
+      if (xcd[g] != q) continue;
+      b->ch_first[g] = (int)cg.size();
+      const int n = b->n[g];
+      for (int lo = 0; lo < n; lo += kChunkRows) {
+        cg.push_back(g);
+        clo.push_back(lo);
+        chi.push_back(std::min(n, lo + kChunkRows));
+      }
+      b->ch_nshort[g] = (int)cg.size() - b->ch_first[g];
+      for (int r = 0; r < b->n_long[g]; ++r) {
+        cg.push_back(g);
+        clo.push_back(b->h_long_rows[b->long_off[g] + r]);
+        chi.push_back(-1);
+      }
+      b->ch_nlong[g] = b->n_long[g];
+    }
+    b->xcount[q] = (int)cg.size() - b->xfirst[q];
+  }
   const size_t nc = cg.size();
-  NVD_TRY(balloc(b, &b->ch_buf, 3 * nc));
+  if (b->ch_buf && (size_t)b->n_chunks != nc) {
+    (void)hipFree(b->ch_buf);
+    b->ch_buf = nullptr;
+  }
+  if (!b->ch_buf) NVD_TRY(balloc(b, &b->ch_buf, 3 * nc));
+  b->n_chunks = (int)nc;
   std::vector<int> h(3 * nc);
   std::copy(cg.begin(), cg.end(), h.begin());
   std::copy(clo.begin(), clo.end(), h.begin() + nc);
   std::copy(chi.begin(), chi.end(), h.begin() + 2 * nc);
   NVD_HIP(hipMemcpyAsync(b->ch_buf, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, s));
   NVD_HIP(hipStreamSynchronize(s));
+  b->ch_xcd = xcd;
   return NVD_OK;
 }
 
@@ -856,6 +904,10 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
   a.T = T;
   a.n_chunks = b->n_chunks;
   a.pstride = pstride;
+  for (int q = 0; q < 8; ++q) {
+    a.xfirst[q] = b->xfirst[q];
+    a.xcount[q] = b->xcount[q];
+  }
   a.sg = reinterpret_cast<const SGraph*>(b->sg_dev);
   a.ch_graph = b->ch_buf;
   a.ch_lo = b->ch_buf + b->n_chunks;
@@ -908,7 +960,10 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
   a.irtol2 = mixed ? o.inner_rtol * o.inner_rtol : o.rtol * o.rtol;
   a.max_iter = o.max_iter;
   a.max_refine = mixed ? o.max_refine : std::max(2, std::min(o.max_refine, 3));
-  const int grid = std::min(b->n_chunks, kSweepGrid);
+  // a multiple of 8 blocks (the same number on every XCD)
+  int xmax = 0;
+  for (int q = 0; q < 8; ++q) xmax = std::max(xmax, b->xcount[q]);
+  const int grid = 8 * std::max(1, std::min(xmax, kSweepGrid / 8));
 
   ks_reset<<<(G + 255) / 256, 256, 0, s>>>(a);
   ks_delta<T><<<grid, SBS, 0, s>>>(a);
@@ -946,6 +1001,15 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
     NVD_HIP(hipMemcpyAsync(info_host, b->info, sizeof(nvd_pair_info) * K, hipMemcpyDeviceToHost, s));
   NVD_HIP(hipStreamSynchronize(s));
   ++b->sweeps;
+  if (info_host) {
+    int off = 0;
+    for (int g = 0; g < G; ++g) {
+      int itmax = 0;
+      for (int j = 0; j < ks[g]; ++j) itmax = std::max(itmax, info_host[off + j].iters);
+      if (itmax > 0) b->it_est[g] = itmax;
+      off += ks[g];
+    }
+  }
   return NVD_OK;
 }
 

@@ -152,6 +152,16 @@ __device__ __forceinline__ void recount_active(ColState* cs, int T) {
   }
 }
 
+// Loads of the CSR (column indices, weights) in the Laplacian apply.
+#ifndef NVD_NT_CSR
+#define NVD_NT_CSR 0
+#endif
+#if NVD_NT_CSR
+#define NVD_CSR_LOAD(p) __builtin_nontemporal_load(p)
+#else
+#define NVD_CSR_LOAD(p) (*(p))
+#endif
+
 // VW consecutive elements of a row, loaded and stored as one access.
 template <typename V, int VW>
 struct VecOf {

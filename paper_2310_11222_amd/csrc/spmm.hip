@@ -263,11 +263,11 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
             col[r][u] = 0;
             wt[r][u] = (V)0;
             if (e < deg[r]) {
-              col[r][u] = __builtin_nontemporal_load(&a.ci[rs[r] + e]);
+              col[r][u] = NVD_CSR_LOAD(&a.ci[rs[r] + e]);
               if constexpr (UNIT)
                 wt[r][u] = (V)1;
               else
-                wt[r][u] = __builtin_nontemporal_load(&a.w[rs[r] + e]);
+                wt[r][u] = NVD_CSR_LOAD(&a.w[rs[r] + e]);
             }
           }
         }
