@@ -201,3 +201,24 @@ def test_sweep_repeatable_and_close_to_persistent():
         xg = X[off:off + g.n * k].reshape(g.n, k)
         assert np.abs(xg.sum(axis=0)).max() <= 1e-9 * np.abs(xg).sum()
         off += g.n * k
+
+
+@pytest.mark.parametrize("persistent", SOLVERS)
+@pytest.mark.parametrize("k,precision", [(1, "mixed"), (2, "fp64"), (3, "mixed"), (16, "fp64"),
+                                         (33, "mixed"), (64, "mixed")])
+def test_tiles_across_widths(k, precision, persistent):
+    """Every tile width the batched solvers instantiate (T = 1, 2, 4, 16, 64:
+    scalar, 8-byte and 16-byte row accesses), unweighted and weighted graphs
+    mixed, against the dense oracle."""
+    sizes = [900, 2100, 350, 1600]
+    graphs, Ps, Qs = _mk_batch(11 + k, sizes, [k] * len(sizes), weighted=(k % 2 == 1))
+    say("batch tiles", k, precision, "persistent" if persistent else "sweep")
+    tol = 1e-8 if precision == "fp64" else 1e-6
+    d, _, info, _ = _run(graphs, Ps, Qs, precision, rtol=1e-10 if precision == "fp64" else 1e-8,
+                         persistent=persistent)
+    off = 0
+    for g, P, Q in zip(graphs, Ps, Qs):
+        ref = oracle.ge_dense(g.n, g.row_ptr, g.col_idx, g.w, P, Q)["d"]
+        assert rel_err(d[off:off + k], ref).max() <= tol, (g.n, k)
+        off += k
+    assert all(i["status"] == 0 for i in info)
