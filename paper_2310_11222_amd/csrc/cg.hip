@@ -446,13 +446,37 @@ __global__ void k_check(int T, double rtol2, ColState* cs) {
   recount_active(cs, T);
 }
 
+// Outer convergence right after a residual pass on a connected graph, from
+// the pass's own dots: ||r - mean||^2 = r.r - n mean^2.  Closes the pairs
+// that converged and those out of refinement steps, so the host can stop
+// without setting up another inner solve.
+__global__ void k_outer_check(int T, int n, double rtol2, int max_refine, ColState* cs) {
+  const int t = threadIdx.x;
+  if (t < T && cs->oactive[t]) {
+    const double m = cs->dots[3][t] / (double)n;
+    const double rr = cs->dots[2][t] - (double)n * m * m;
+    if (rr <= rtol2 * cs->obnorm2[t]) {
+      cs->oactive[t] = 0;
+    } else if (cs->refine[t] >= max_refine) {
+      cs->oactive[t] = 0;
+      cs->status[t] = kStNoconv;
+    }
+  }
+  recount_active(cs, T);
+}
+
 // d^2 = delta_bar^T x + x^T r from the last residual pass; d = sqrt(max(d^2, 0)).
+// shift_n > 0: that pass saw x before its mean was removed (connected graph
+// of shift_n nodes).  Shifting x by -m (m = sum x / n) leaves r unchanged
+// (L 1 = 0) and changes delta_bar^T x by -m sum(delta_bar) = 0, so only x^T r
+// changes, by -m sum(r).
 __global__ void k_finish(int T, int mark_open_noconv, ColState* cs, double* d_out,
-                         nvd_pair_info* info) {
+                         nvd_pair_info* info, int shift_n) {
   const int t = threadIdx.x;
   if (t >= T) return;
   const double bx = cs->dots[0][t];
-  const double xr = cs->dots[1][t];
+  double xr = cs->dots[1][t];
+  if (shift_n > 0) xr -= cs->dots[4][t] / (double)shift_n * cs->dots[3][t];
   const double rr = cs->dots[2][t];
   const double bb = cs->obnorm2[t];
   double dsq = bx + xr;
@@ -796,6 +820,7 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
     have_x = true;
   }
 
+  int shift_n = 0;   // > 0: x's mean is removed after the last residual pass
   if (!mixed) {
     if (have_x) {
       // r = delta_bar - L x0, then CG from there
@@ -825,16 +850,24 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
     }
   } else {
     const double irtol2 = sp.inner_rtol * sp.inner_rtol;
+    const bool connected = g->n_comp == 1;
     bool first = !have_x;
+    bool resid_current = false;   // the last residual pass saw the current x
     for (int step = 0; step <= sp.max_refine; ++step) {
       MeanSrc mr{};
       const double* src = ws->b64;
       if (!first) {
         // (a7) FP64 outer residual r = delta_bar - L x, projected
         NVD_TRY(launch_spmm(resid, ws->red, s));
-        if (g->n_comp == 1) {
+        resid_current = true;
+        if (connected) {
           mr.n = n;
           mr.dots_sum = ws->cs->dots[3];
+          k_outer_check<<<1, 64, 0, s>>>(T, n, rtol2, sp.max_refine, ws->cs);
+          NVD_HIP(hipGetLastError());
+          int no = 0;
+          NVD_TRY(poll(ws, s, nullptr, &no));
+          if (no == 0) break;
         } else {
           NVD_TRY(mean_into(g, ws, T, ProjSrc{ws->r64, T, nullptr, 0}, &mr, s));
         }
@@ -844,27 +877,40 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
                                             ws->p32, ws->q32, rtol2, irtol2, sp.max_refine,
                                             first ? 1 : 0, ws->cs, ws->red);
       NVD_HIP(hipGetLastError());
+      if (first || !connected) {
+        int no = 0;
+        NVD_TRY(poll(ws, s, nullptr, &no));
+        if (no == 0) break;
+      }
       first = false;
-      int no = 0;
-      NVD_TRY(poll(ws, s, nullptr, &no));
-      if (no == 0) break;
+      // (an inner set-up that closed every pair leaves nothing active: the
+      // first chunk of the loop returns at once)
       NVD_TRY(cg_loop<float>(g, ws, T, ws->x32, ws->r32, ws->p32, ws->q32, g->invd32, irtol2,
                              sp.max_iter, sp, s));
       NVD_TILE_SWITCH(T, (k_accum<TT><<<grid, kBS, 0, s>>>(cap, ws->x64, ws->x32, ws->cs)));
       NVD_HIP(hipGetLastError());
+      resid_current = false;
     }
-    MeanSrc mx{};
-    NVD_TRY(mean_into(g, ws, T, ProjSrc{ws->x64, T, nullptr, 0}, &mx, s));
-    NVD_TILE_SWITCH(T, (k_xfinal<TT><<<grid, kBS, 0, s>>>(n, ws->x64, mx, nullptr, 0)));
-    NVD_TRY(launch_spmm(resid, ws->red, s));
+    if (connected && resid_current) {
+      // the last residual pass is that of the final x: its dots give the
+      // distance once x's mean is accounted for (k_finish); x itself is
+      // shifted only where it is returned
+      shift_n = n;
+    } else {
+      MeanSrc mx{};
+      NVD_TRY(mean_into(g, ws, T, ProjSrc{ws->x64, T, nullptr, 0}, &mx, s));
+      NVD_TILE_SWITCH(T, (k_xfinal<TT><<<grid, kBS, 0, s>>>(n, ws->x64, mx, nullptr, 0)));
+      NVD_TRY(launch_spmm(resid, ws->red, s));
+    }
   }
   // (a8) quadratic form, distances, per-pair info; copy x out
   if (X) {
-    MeanSrc none{};
-    none.n = n;
-    NVD_TILE_SWITCH(T, (k_xfinal<TT><<<grid, kBS, 0, s>>>(n, ws->x64, none, X, ldx)));
+    MeanSrc xm{};
+    xm.n = n;
+    if (shift_n > 0) xm.dots_sum = ws->cs->dots[4];
+    NVD_TILE_SWITCH(T, (k_xfinal<TT><<<grid, kBS, 0, s>>>(n, ws->x64, xm, X, ldx)));
   }
-  k_finish<<<1, 64, 0, s>>>(T, mixed ? 0 : 1, ws->cs, d_out, info_dev);
+  k_finish<<<1, 64, 0, s>>>(T, mixed ? 0 : 1, ws->cs, d_out, info_dev, shift_n);
   NVD_HIP(hipGetLastError());
   return NVD_OK;
 }
