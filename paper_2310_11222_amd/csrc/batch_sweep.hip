@@ -41,6 +41,7 @@ struct SGraph {
 // Per (graph, column) state, index g*T + c, and per-graph flags.
 struct SState {
   double *rho, *alpha, *beta, *bn2, *obn2, *mean, *itol2;
+  double* xm;        // mean of x seen by the graph's last residual pass
   int *act, *oact, *it, *itc, *ref, *stat;
   int* g_act;        // graph has an inner CG column running
   int* g_oact;       // graph has a pair not yet converged
@@ -177,6 +178,25 @@ __device__ __forceinline__ const V* invd_ptr(const SArgs& a) {
     return reinterpret_cast<const V*>(a.invd32);
 }
 
+// Distance and info of pair t of graph g from the FP64 dots of a residual
+// pass: d^2 = delta_bar^T x + x^T r (0 when delta_bar = 0).
+__device__ __forceinline__ void write_pair(const SArgs& a, const SGraph& sg, int g, int t, double bx,
+                                           double xr, double rr) {
+  const int i = g * a.T + t;
+  const double bb = a.s.obn2[i];
+  const double dsq = bb > 0.0 ? bx + xr : 0.0;
+  a.d_out[sg.out_off + t] = sqrt(dsq > 0.0 ? dsq : 0.0);
+  nvd_pair_info pi;
+  pi.status = a.s.stat[i];
+  pi.iters = a.s.it[i];
+  pi.refine_steps = a.s.ref[i];
+  pi.reserved = 0;
+  pi.rel_res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+  pi.dsq_plain = bb > 0.0 ? bx : 0.0;
+  pi.dsq = dsq;
+  a.info[sg.out_off + t] = pi;
+}
+
 // ---------------------------------------------------------------------------
 // set-up: delta = P - Q, its mean, delta_bar, ||delta_bar||
 // ---------------------------------------------------------------------------
@@ -256,6 +276,9 @@ __global__ __launch_bounds__(SBS) void ks_proj(SArgs a) {
         a.s.ref[i] = 0;
         a.s.stat[i] = kStOk;
         a.s.mean[i] = 0.0;
+        a.s.xm[i] = 0.0;
+        // pairs with delta_bar = 0 are final now: d = 0, x = 0
+        if (t < sg.k && !a.s.oact[i]) write_pair(a, sg, g, t, 0.0, 0.0, 0.0);
       }
       recount_graph(a, g);
     }
@@ -266,8 +289,12 @@ __global__ __launch_bounds__(SBS) void ks_proj(SArgs a) {
 // ---------------------------------------------------------------------------
 // Laplacian apply over chunks
 //   EPI_CG:              q = L p (V), dot p.q -> alpha
-//   EPI_RESID, ND == 2:  r = delta_bar - L x (FP64), sum r, r.r -> outer check
-//   EPI_RESID, ND == 4:  final pass of every graph: + delta_bar.x, x.r -> d
+//   EPI_RESID, ND == 5:  r = delta_bar - L x (FP64) on the open graphs; sum r,
+//                        r.r, delta_bar.x, x.r, sum x -> outer check, and d of
+//                        every pair of the graph for the current x (the mean
+//                        of x accounted for: the graph's last pass is final)
+//   EPI_RESID, ND == 4:  pass over every graph after x was made mean-zero:
+//                        delta_bar.x, x.r -> d
 // ---------------------------------------------------------------------------
 template <typename V, int T, int EPI, int ND>
 __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
@@ -280,7 +307,7 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
   using VV = typename VecOf<V, VW>::type;
   constexpr int SHN = (SBS / 64) * ND * T > SBS * VW ? (SBS / 64) * ND * T : SBS * VW;
   __shared__ double sh[SHN];
-  __shared__ double vals[4 * kMaxTile];
+  __shared__ double vals[5 * kMaxTile];
   __shared__ double red[SBS];
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -300,7 +327,7 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
     const int g = a.ch_graph[ch];
     if constexpr (EPI == EPI_CG) {
       if (!a.s.g_act[g]) continue;
-    } else if constexpr (ND == 2) {
+    } else if constexpr (ND == 5) {
       if (!a.s.g_oact[g]) continue;
     }
     const SGraph sg = a.sg[g];
@@ -347,10 +374,9 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
           rv[v] = (V)rr;
           acc[0][v] += rr;
           acc[1][v] += rr * rr;
-          if constexpr (ND == 4) {
-            acc[2][v] += bb[v] * (double)own[v];
-            acc[3][v] += (double)own[v] * rr;
-          }
+          acc[2][v] += bb[v] * (double)own[v];
+          acc[3][v] += (double)own[v] * rr;
+          if constexpr (ND == 5) acc[4][v] += (double)own[v];
         }
         __builtin_nontemporal_store(pack<V, VW>(rv), yp);
       }
@@ -447,7 +473,7 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
             }
           }
           a.s.alpha[i] = al;
-        } else if constexpr (ND == 2) {
+        } else if constexpr (ND == 5) {
           const double m = vals[t] / (double)sg.n;
           a.s.mean[i] = m;
           const double rr = vals[T + t] - (double)sg.n * m * m;   // ||r - mean||^2
@@ -456,25 +482,16 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
             a.s.oact[i] = 0;
             a.s.stat[i] = kStNoconv;
           }
+          // x - mx has the same residual (L 1 = 0) and the same
+          // delta_bar^T x (delta_bar sums to 0), so only x^T r moves
+          const double mx = vals[4 * T + t] / (double)sg.n;
+          a.s.xm[i] = mx;
+          if (t < sg.k) write_pair(a, sg, g, t, vals[2 * T + t], vals[3 * T + t] - mx * vals[t], vals[T + t]);
         } else {
-          if (t < sg.k) {
-            const double bb = a.s.obn2[i];
-            const double bx = vals[2 * T + t], xr = vals[3 * T + t], rr = vals[T + t];
-            const double dsq = bb > 0.0 ? bx + xr : 0.0;
-            a.d_out[sg.out_off + t] = sqrt(dsq > 0.0 ? dsq : 0.0);
-            nvd_pair_info pi;
-            pi.status = a.s.stat[i];
-            pi.iters = a.s.it[i];
-            pi.refine_steps = a.s.ref[i];
-            pi.reserved = 0;
-            pi.rel_res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-            pi.dsq_plain = bb > 0.0 ? bx : 0.0;
-            pi.dsq = dsq;
-            a.info[sg.out_off + t] = pi;
-          }
+          if (t < sg.k) write_pair(a, sg, g, t, vals[2 * T + t], vals[3 * T + t], vals[T + t]);
         }
       }
-      if constexpr (EPI == EPI_CG || ND == 2) recount_graph(a, g);
+      if constexpr (EPI == EPI_CG || ND == 5) recount_graph(a, g);
     }
     __syncthreads();
   }
@@ -698,7 +715,10 @@ __global__ __launch_bounds__(SBS) void ks_xmean(SArgs a) {
     for (long e = (long)lo * T + t; e < (long)hi * T; e += SBS) acc[0][0] += x[e];
     chunk_block_sum<1, 1>(acc, T, sh, vals);
     if (chunk_arrive<1>(a, ch, g, sg.first, sg.nshort, vals, red)) {
-      if (t < T) a.s.mean[g * T + t] = vals[t] / (double)sg.n;
+      if (t < T) {
+        a.s.mean[g * T + t] = vals[t] / (double)sg.n;
+        a.s.xm[g * T + t] = 0.0;   // x is shifted in place
+      }
     }
     __syncthreads();
   }
@@ -720,7 +740,8 @@ __global__ __launch_bounds__(SBS) void ks_xsub(SArgs a) {
   }
 }
 
-// X (caller's layout: graph-major, n x k per graph) from x
+// X (caller's layout: graph-major, n x k per graph) = x - (its mean where the
+// last residual pass left it in x)
 template <int T>
 __global__ __launch_bounds__(SBS) void ks_xout(SArgs a) {
   const int t = threadIdx.x;
@@ -733,9 +754,10 @@ __global__ __launch_bounds__(SBS) void ks_xout(SArgs a) {
     if (c >= sg.k) continue;
     const int lo = a.ch_lo[ch];
     const double* x = a.x64 + sg.node_off * T;
+    const double m = a.s.xm[g * T + c];
     for (long e = (long)lo * T + t; e < (long)hi * T; e += SBS) {
       const long i = e / T;
-      a.X[sg.in_off + i * sg.k + c] = x[e];
+      a.X[sg.in_off + i * sg.k + c] = x[e] - m;
     }
   }
 }
@@ -845,7 +867,7 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
     b->cap_vsize = (int)vsz;
   }
   // per-chunk partials and per-(graph, column) state
-  const int pstride = 4 * T;
+  const int pstride = 5 * T;
   const size_t need_part = (size_t)b->n_chunks * pstride;
   if (b->spart_cap < need_part) {
     if (b->spart) (void)hipFree(b->spart);
@@ -854,7 +876,7 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
     b->spart_cap = need_part;
   }
   const size_t GT = (size_t)G * T;
-  const size_t state_bytes = GT * (7 * sizeof(double) + 6 * sizeof(int)) + (size_t)G * 3 * sizeof(int) +
+  const size_t state_bytes = GT * (8 * sizeof(double) + 6 * sizeof(int)) + (size_t)G * 3 * sizeof(int) +
                              2 * sizeof(int) + 64;
   if (b->sstate_cap < state_bytes) {
     if (b->sstate) (void)hipFree(b->sstate);
@@ -939,6 +961,7 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
     a.s.obn2 = take_d();
     a.s.mean = take_d();
     a.s.itol2 = take_d();
+    a.s.xm = take_d();
     a.s.act = take_i(GT);
     a.s.oact = take_i(GT);
     a.s.it = take_i(GT);
@@ -969,11 +992,17 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
   ks_delta<T><<<grid, SBS, 0, s>>>(a);
   ks_proj<T><<<grid, SBS, 0, s>>>(a);
   NVD_HIP(hipGetLastError());
+  // Every graph's results are written when its last pair closes: by the
+  // projection (delta_bar = 0) or by a residual pass, which sees the final x.
+  bool closed = false;
   for (int step = 0; step <= a.max_refine; ++step) {
-    if (step > 0) ks_spmm<double, T, EPI_RESID, 2><<<grid, SBS, 0, s>>>(a);
+    if (step > 0) ks_spmm<double, T, EPI_RESID, 5><<<grid, SBS, 0, s>>>(a);
     int n_act = 0, n_oact = 0;
     NVD_TRY(poll_counts(b, a, s, &n_act, &n_oact));
-    if (n_oact == 0) break;
+    if (n_oact == 0) {
+      closed = true;
+      break;
+    }
     ks_inner_init<V, T><<<grid, SBS, 0, s>>>(a, step == 0 ? 1 : 0);
     int done = 0;
     int chunk = 8;
@@ -992,9 +1021,12 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
     }
     ks_accum<V, T><<<grid, SBS, 0, s>>>(a);
   }
-  ks_xmean<T><<<grid, SBS, 0, s>>>(a);
-  ks_xsub<T><<<grid, SBS, 0, s>>>(a);
-  ks_spmm<double, T, EPI_RESID, 4><<<grid, SBS, 0, s>>>(a);
+  if (!closed) {
+    // pairs still open after the last step: results of the final x
+    ks_xmean<T><<<grid, SBS, 0, s>>>(a);
+    ks_xsub<T><<<grid, SBS, 0, s>>>(a);
+    ks_spmm<double, T, EPI_RESID, 4><<<grid, SBS, 0, s>>>(a);
+  }
   if (X) ks_xout<T><<<grid, SBS, 0, s>>>(a);
   NVD_HIP(hipGetLastError());
   if (info_host)
