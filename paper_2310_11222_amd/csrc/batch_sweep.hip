@@ -31,7 +31,10 @@ constexpr int SBS = 256;          // threads per block of the sweep kernels
 #define NVD_CHUNK_ROWS 1024
 #endif
 constexpr int kChunkRows = NVD_CHUNK_ROWS;   // rows per short chunk
-constexpr int kSweepGrid = 2048;  // blocks per sweep kernel at most
+// Blocks per sweep kernel at most.  One block per chunk is best measured:
+// the dispatcher then balances the uneven chunk costs (long rows, skipped
+// graphs) better than a grid-stride loop.
+constexpr int kSweepGrid = 1 << 20;
 
 struct SGraph {
   int n, k, weighted, first, nshort, nlong, out_off, pad;
@@ -983,7 +986,7 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
   a.irtol2 = mixed ? o.inner_rtol * o.inner_rtol : o.rtol * o.rtol;
   a.max_iter = o.max_iter;
   a.max_refine = mixed ? o.max_refine : std::max(2, std::min(o.max_refine, 3));
-  // a multiple of 8 blocks (the same number on every XCD)
+  // a multiple of 8 blocks (the same number on every XCD): one per chunk
   int xmax = 0;
   for (int q = 0; q < 8; ++q) xmax = std::max(xmax, b->xcount[q]);
   const int grid = 8 * std::max(1, std::min(xmax, kSweepGrid / 8));
