@@ -20,7 +20,10 @@ namespace nvd {
 constexpr int kMaxTile = 64;        // columns per SpMM pass / solver tile
 constexpr int kBS = 256;            // threads per block for the streaming kernels
 constexpr int kGrp = 32;            // blocks per first-level reduction group
-constexpr int kMaxBlocks = 4096;    // grid cap for kernels that reduce
+#ifndef NVD_MAX_BLOCKS
+#define NVD_MAX_BLOCKS 8192
+#endif
+constexpr int kMaxBlocks = NVD_MAX_BLOCKS;   // grid cap for kernels that reduce
 constexpr int kMaxDots = 6;         // dot products reduced by one kernel
 constexpr int kRedStride = kMaxDots * 64;  // doubles per block in the reduction scratch
 constexpr int kLongRow = 128;       // rows with more neighbours take the split-row path

@@ -66,6 +66,8 @@ struct SpmmGeom {
 #endif
 constexpr int kSpmmR = NVD_SPMM_R;
 // Short-row blocks at most (the rest of kMaxBlocks is left to long rows).
+// Small row chunks per block let the dispatcher balance the work; more
+// blocks than this lengthen the grid reduction's tail.
 constexpr int kSpmmMaxShortGrid = kMaxBlocks - 1024;
 
 // Epilogue for VW columns c0 .. c0+VW-1 of one row; sum = (A x) entries.
