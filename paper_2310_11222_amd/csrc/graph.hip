@@ -1,14 +1,16 @@
 // Graph handle: host validation of the CSR, self-loop removal, upload,
 // weighted degrees and inverse degrees (on the device), connected
-// components (host breadth-first search), the split-row work list, and the
-// cached solver workspace.
+// components (host union-find), the split-row work list, and the cached
+// solver workspace.  The host passes run on row ranges in parallel.
 //
 // The paper builds L = D - A from the simplified (undirected, simple) graph
 // and does not count this preprocessing in its timings (section 5.2).
 #include <algorithm>
 #include <cmath>
+#include <climits>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "device_common.hpp"
 
@@ -146,6 +148,31 @@ nvd_status ensure_workspace(DevGraph* g, int tile, bool need32) {
 // ---------------------------------------------------------------------------
 // creation
 // ---------------------------------------------------------------------------
+// Host threads for the set-up passes (one for small graphs).
+static int host_threads(size_t work) {
+  if (work < ((size_t)1 << 18)) return 1;
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int t = hw ? (int)hw : 4;
+  return std::max(1, std::min(t, 16));
+}
+
+// f(lo, hi, tid) on nt contiguous row ranges of [0, n), in parallel.
+template <class F>
+static void parallel_rows(int n, int nt, F&& f) {
+  if (nt <= 1 || n < 2 * nt) {
+    f(0, n, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    const int lo = t * chunk, hi = std::min(n, lo + chunk);
+    if (lo >= hi) break;
+    th.emplace_back([&f, lo, hi, t]() { f(lo, hi, t); });
+  }
+  for (auto& x : th) x.join();
+}
+
 static nvd_status build_graph(int64_t n64, int64_t nnz64, const int64_t* row_ptr,
                               const int32_t* col_idx, const double* wts, hipStream_t stream,
                               DevGraph** out) {
@@ -178,99 +205,205 @@ static nvd_status build_graph(int64_t n64, int64_t nnz64, const int64_t* row_ptr
       return NVD_E_GRAPH;
     }
   }
-  // drop self-loops, sort each row by column, check range / repeats / weights
-  std::vector<int> rp(n + 1, 0), ci;
-  std::vector<double> w;
-  std::vector<int> in_pos;
-  ci.reserve(nnz_in);
-  if (wts) w.reserve(nnz_in);
-  in_pos.reserve(nnz_in);
-  int self_loops = 0;
-  std::vector<std::pair<int, int>> rowbuf;
-  for (int i = 0; i < n; ++i) {
-    rowbuf.clear();
-    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-      const int c = col_idx[e];
-      if (c < 0 || c >= n) {
-        set_error("nvd_graph_create: column " + std::to_string(c) + " out of range in row " +
-                  std::to_string(i));
-        return NVD_E_GRAPH;
-      }
-      if (wts) {
-        const double wv = wts[e];
-        if (!(wv > 0.0) || !std::isfinite(wv)) {
-          set_error("nvd_graph_create: weight of entry " + std::to_string(e) +
-                    " is not a finite positive number");
-          return NVD_E_GRAPH;
+  // drop self-loops, sort each row by column, check range / repeats /
+  // weights, check symmetry, find the components: row ranges in parallel.
+  // Errors name the lowest offending row, as a sequential scan would.
+  const int nt = host_threads((size_t)nnz_in + (size_t)n);
+  struct RowErr {
+    int row = INT32_MAX;
+    int kind = 0;        // 1 column range, 2 weight, 3 repeated entry, 4 no mirror, 5 weights differ
+    int64_t e = 0;
+    int a = 0, b = 0;
+  };
+  auto keep = [](RowErr& r, int row, int kind, int64_t e, int a, int b) {
+    if (row < r.row) r = RowErr{row, kind, e, a, b};
+  };
+  auto report = [&](const RowErr& r) -> nvd_status {
+    switch (r.kind) {
+      case 1:
+        set_error("nvd_graph_create: column " + std::to_string(r.a) + " out of range in row " +
+                  std::to_string(r.row));
+        break;
+      case 2:
+        set_error("nvd_graph_create: weight of entry " + std::to_string(r.e) +
+                  " is not a finite positive number");
+        break;
+      case 3:
+        set_error("nvd_graph_create: repeated entry (" + std::to_string(r.row) + ", " +
+                  std::to_string(r.a) + ")");
+        break;
+      case 4:
+        set_error("nvd_graph_create: entry (" + std::to_string(r.row) + ", " + std::to_string(r.a) +
+                  ") has no mirror (" + std::to_string(r.a) + ", " + std::to_string(r.row) + ")");
+        break;
+      default:
+        set_error("nvd_graph_create: weights of (" + std::to_string(r.row) + ", " +
+                  std::to_string(r.a) + ") and its mirror differ");
+        break;
+    }
+    return NVD_E_GRAPH;
+  };
+  // pass 1: entries kept per row, range and weight checks, sorted rows
+  std::vector<int> rp(n + 1, 0);
+  std::vector<char> sorted_row(n, 1);
+  std::vector<RowErr> err1(nt);
+  std::vector<int> loops_t(nt, 0);
+  parallel_rows(n, nt, [&](int lo, int hi, int tid) {
+    RowErr& er = err1[tid];
+    int loops = 0;
+    for (int i = lo; i < hi && i < er.row; ++i) {
+      int kept = 0, prev = -1;
+      bool srt = true;
+      for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+        const int c = col_idx[e];
+        if (c < 0 || c >= n) {
+          keep(er, i, 1, e, c, 0);
+          break;
         }
+        if (wts) {
+          const double wv = wts[e];
+          if (!(wv > 0.0) || !std::isfinite(wv)) {
+            keep(er, i, 2, e, c, 0);
+            break;
+          }
+        }
+        if (c == i) {
+          ++loops;
+          continue;
+        }
+        if (c <= prev) srt = false;
+        prev = c;
+        ++kept;
       }
-      if (c == i) {
-        ++self_loops;
+      rp[i + 1] = kept;
+      sorted_row[i] = srt;
+    }
+    loops_t[tid] = loops;
+  });
+  RowErr first_err;
+  for (const RowErr& r : err1)
+    if (r.row < first_err.row) first_err = r;
+  const int self_loops = std::accumulate(loops_t.begin(), loops_t.end(), 0);
+  for (int i = 0; i < n; ++i) rp[i + 1] += rp[i];
+  const int nnz = rp[n];
+  // pass 2: kept entries in column order (rows before the first pass-1 error)
+  std::vector<int> ci(nnz), in_pos(nnz);
+  std::vector<double> w(wts ? nnz : 0);
+  std::vector<RowErr> err2(nt);
+  const int rows2 = first_err.row < n ? first_err.row : n;
+  parallel_rows(rows2, nt, [&](int lo, int hi, int tid) {
+    RowErr& er = err2[tid];
+    std::vector<std::pair<int, int>> rowbuf;
+    for (int i = lo; i < hi && i < er.row; ++i) {
+      int o = rp[i];
+      if (sorted_row[i]) {
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+          const int c = col_idx[e];
+          if (c == i) continue;
+          ci[o] = c;
+          in_pos[o] = (int)e;
+          if (wts) w[o] = wts[e];
+          ++o;
+        }
         continue;
       }
-      rowbuf.emplace_back(c, (int)e);
-    }
-    std::sort(rowbuf.begin(), rowbuf.end());
-    for (size_t k = 0; k < rowbuf.size(); ++k) {
-      if (k > 0 && rowbuf[k].first == rowbuf[k - 1].first) {
-        set_error("nvd_graph_create: repeated entry (" + std::to_string(i) + ", " +
-                  std::to_string(rowbuf[k].first) + ")");
-        return NVD_E_GRAPH;
-      }
-      ci.push_back(rowbuf[k].first);
-      in_pos.push_back(rowbuf[k].second);
-      if (wts) w.push_back(wts[rowbuf[k].second]);
-    }
-    rp[i + 1] = (int)ci.size();
-  }
-  const int nnz = (int)ci.size();
-  // symmetry with equal weights: every (i, j) has a matching (j, i)
-  for (int i = 0; i < n; ++i) {
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-      const int j = ci[e];
-      const int* b = ci.data() + rp[j];
-      const int* en = ci.data() + rp[j + 1];
-      const int* f = std::lower_bound(b, en, i);
-      if (f == en || *f != i) {
-        set_error("nvd_graph_create: entry (" + std::to_string(i) + ", " + std::to_string(j) +
-                  ") has no mirror (" + std::to_string(j) + ", " + std::to_string(i) + ")");
-        return NVD_E_GRAPH;
-      }
-      if (wts && w[f - ci.data()] != w[e]) {
-        set_error("nvd_graph_create: weights of (" + std::to_string(i) + ", " +
-                  std::to_string(j) + ") and its mirror differ");
-        return NVD_E_GRAPH;
+      rowbuf.clear();
+      for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+        if (col_idx[e] != i) rowbuf.emplace_back(col_idx[e], (int)e);
+      std::sort(rowbuf.begin(), rowbuf.end());
+      for (size_t k = 0; k < rowbuf.size(); ++k) {
+        if (k > 0 && rowbuf[k].first == rowbuf[k - 1].first) {
+          keep(er, i, 3, 0, rowbuf[k].first, 0);
+          break;
+        }
+        ci[o] = rowbuf[k].first;
+        in_pos[o] = rowbuf[k].second;
+        if (wts) w[o] = wts[rowbuf[k].second];
+        ++o;
       }
     }
-  }
-  // connected components by breadth-first search, labelled in order of
-  // their smallest node
-  std::vector<int> comp(n, -1), perm;
-  perm.reserve(n);
-  std::vector<int> comp_off(1, 0);
-  int ncomp = 0, nisol = 0, maxdeg = 0;
-  for (int s = 0; s < n; ++s) {
-    maxdeg = std::max(maxdeg, rp[s + 1] - rp[s]);
-    if (rp[s + 1] == rp[s]) ++nisol;
-    if (comp[s] >= 0) continue;
-    const size_t head0 = perm.size();
-    comp[s] = ncomp;
-    perm.push_back(s);
-    for (size_t h = head0; h < perm.size(); ++h) {
-      const int v = perm[h];
-      for (int e = rp[v]; e < rp[v + 1]; ++e) {
-        const int u = ci[e];
-        if (comp[u] < 0) {
-          comp[u] = ncomp;
-          perm.push_back(u);
+  });
+  for (const RowErr& r : err2)
+    if (r.row < first_err.row) first_err = r;
+  if (first_err.row < n) return report(first_err);
+  // pass 3: symmetry with equal weights: every (i, j) has a matching (j, i)
+  std::vector<RowErr> err3(nt);
+  parallel_rows(n, nt, [&](int lo, int hi, int tid) {
+    RowErr& er = err3[tid];
+    for (int i = lo; i < hi && i < er.row; ++i) {
+      for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int j = ci[e];
+        const int* b = ci.data() + rp[j];
+        const int* en = ci.data() + rp[j + 1];
+        const int* f = std::lower_bound(b, en, i);
+        if (f == en || *f != i) {
+          keep(er, i, 4, 0, j, 0);
+          break;
+        }
+        if (wts && w[f - ci.data()] != w[e]) {
+          keep(er, i, 5, 0, j, 0);
+          break;
         }
       }
     }
-    // keep each component's node list sorted (ascending ids)
-    std::sort(perm.begin() + head0, perm.end());
-    comp_off.push_back((int)perm.size());
-    ++ncomp;
+  });
+  for (const RowErr& r : err3)
+    if (r.row < first_err.row) first_err = r;
+  if (first_err.row < n) return report(first_err);
+  // connected components: concurrent union-find that always hangs the larger
+  // root under the smaller one, so every component's root is its smallest
+  // node; components are numbered in order of that node
+  std::vector<int> parent(n);
+  std::iota(parent.begin(), parent.end(), 0);
+  auto find = [&](int x) {
+    for (;;) {
+      const int p = __atomic_load_n(&parent[x], __ATOMIC_RELAXED);
+      if (p == x) return x;
+      const int gp = __atomic_load_n(&parent[p], __ATOMIC_RELAXED);
+      if (gp != p) {
+        int expect = p;
+        __atomic_compare_exchange_n(&parent[x], &expect, gp, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED);
+      }
+      x = p;
+    }
+  };
+  parallel_rows(n, nt, [&](int lo, int hi, int) {
+    for (int i = lo; i < hi; ++i) {
+      for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        int u = i, v = ci[e];
+        if (v < u) continue;     // each undirected edge once
+        for (;;) {
+          u = find(u);
+          v = find(v);
+          if (u == v) break;
+          if (u < v) std::swap(u, v);   // u: the larger root
+          int expect = u;
+          if (__atomic_compare_exchange_n(&parent[u], &expect, v, false, __ATOMIC_ACQ_REL,
+                                          __ATOMIC_RELAXED))
+            break;
+        }
+      }
+    }
+  });
+  std::vector<int> comp(n);
+  parallel_rows(n, nt, [&](int lo, int hi, int) {
+    for (int i = lo; i < hi; ++i) comp[i] = find(i);
+  });
+  int ncomp = 0, nisol = 0, maxdeg = 0;
+  std::vector<int> comp_id(n, -1);
+  for (int i = 0; i < n; ++i) {
+    if (comp[i] == i) comp_id[i] = ncomp++;
+    maxdeg = std::max(maxdeg, rp[i + 1] - rp[i]);
+    if (rp[i + 1] == rp[i]) ++nisol;
   }
+  std::vector<int> comp_off(ncomp + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    comp[i] = comp_id[comp[i]];
+    ++comp_off[comp[i] + 1];
+  }
+  for (int c = 0; c < ncomp; ++c) comp_off[c + 1] += comp_off[c];
+  std::vector<int> perm(n), fill(comp_off.begin(), comp_off.end() - 1);
+  for (int i = 0; i < n; ++i) perm[fill[comp[i]]++] = i;   // ascending ids within a component
   // split-row segments
   std::vector<int> seg_row, seg_lo, seg_hi, seg_first, seg_cnt;
   int nlong = 0;

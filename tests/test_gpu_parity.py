@@ -73,6 +73,42 @@ def test_graph_setup_degrees_and_components():
     assert st["n_comp"] == ref.max() + 1 and st["n_isolated"] == 3   # nodes n+1..n+3
 
 
+def test_large_disconnected_components_and_solve():
+    """Set-up of a graph large enough for the parallel host passes: three BA
+    components of uneven size plus isolated nodes, randomly relabelled and
+    given unsorted rows; labels (numbered by smallest node), degrees and a
+    mixed solve against the oracle's per-component definition."""
+    rng = np.random.default_rng(21)
+    parts = [barabasi_albert(n, 3, rng) for n in (150000, 90000, 40000)]
+    offs = np.cumsum([0] + [p.n for p in parts])
+    n = int(offs[-1]) + 5                         # 5 isolated nodes
+    eu = np.concatenate([p.eu + o for p, o in zip(parts, offs[:-1])])
+    ev = np.concatenate([p.ev + o for p, o in zip(parts, offs[:-1])])
+    perm = rng.permutation(n)
+    g0 = Graph(n, perm[eu], perm[ev])
+    # shuffle the entries inside every row (the library sorts them)
+    ci = g0.col_idx.copy()
+    for i in rng.choice(n, 2000, replace=False):
+        a, b = g0.row_ptr[i], g0.row_ptr[i + 1]
+        ci[a:b] = rng.permutation(ci[a:b])
+    say("large disconnected", n, g0.nnz)
+    import paper_2310_11222_amd as nvd
+    dg = nvd.Graph(g0.row_ptr, ci, None)
+    lab, deg = dg.query()
+    ref = oracle.components(n, g0.row_ptr, g0.col_idx)
+    assert np.array_equal(lab, ref)
+    np.testing.assert_array_equal(deg, np.diff(g0.row_ptr).astype(np.float64))
+    st = dg.stats()
+    assert st["n_comp"] == 3 + 5 and st["n_isolated"] == 5
+    k = 4
+    P = np.where(rng.random((n, k)) < 0.05, rng.random((n, k)), 0.0)
+    Q = np.where(rng.random((n, k)) < 0.05, rng.random((n, k)), 0.0)
+    d, _, info = dg.distances(P, Q, precision="mixed", rtol=1e-8)
+    r = oracle.ge_pcg(n, g0.row_ptr, g0.col_idx, None, P, Q)
+    assert rel_err(d.cpu().numpy(), r["d"]).max() <= 1e-6
+    assert all(i["status"] == 0 for i in info)
+
+
 @pytest.mark.parametrize("k", [1, 5, 64])
 def test_project_matches_oracle(k):
     g = _hub_graph(3)
