@@ -24,6 +24,8 @@ pseudoinverse.  The paper replaces the pseudoinverse by a Laplacian solve
 * ``closed_forms`` -- textbook effective resistances (path, cycle, complete,
                     star, complete bipartite, weighted tree).
 * ``grad``       -- gradients of d^2 with respect to a, b and the edge weights.
+* ``pairwise``   -- all pairwise distances among m node vectors (dense and
+                    per-pair PCG routes).
 
 Parity status: every function here is pinned by tests against closed forms,
 special cases, invariants or an independent route; none is "parity unpinned".
@@ -36,6 +38,7 @@ from .tree import ge_tree
 from .cycle import ge_cycle
 from . import closed_forms
 from .grad import grad_dense
+from .pairwise import pairwise_dense, pairwise_pcg
 
 __all__ = ["laplacian_dense", "laplacian_sparse", "components", "project",
            "ge_dense", "ge_grounded", "ge_pcg", "ge_tree", "ge_cycle",

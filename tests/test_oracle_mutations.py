@@ -164,6 +164,26 @@ def pin_suite(o):
         check("grad-fd", ok)
     except Exception:
         failed.append("grad-raised")
+    # all pairwise distances: path closed form (both routes), a disconnected
+    # graph against the per-pair grounded route, and the metric invariants
+    try:
+        gp = path_graph(9)
+        want = np.sqrt(np.abs(np.subtract.outer(np.arange(9), np.arange(9))).astype(float))
+        for route in ("pairwise_dense", "pairwise_pcg"):
+            D = getattr(o, route)(gp.n, gp.row_ptr, gp.col_idx, None, np.eye(9))
+            check("pairwise-path-" + route, close(D, want))
+        Vd = np.random.default_rng(10).random((N, 5))
+        D = o.pairwise_dense(N, gd.row_ptr, gd.col_idx, None, Vd)
+        iu, ju = np.triu_indices(5, 1)
+        ref = o.ge_grounded(N, gd.row_ptr, gd.col_idx, None, Vd[:, iu], Vd[:, ju])["d"]
+        check("pairwise-disconnected", close(D[iu, ju], ref) and close(D, D.T) and
+              np.all(np.diag(D) == 0.0))
+        ok = True
+        for i, j, k in itertools.permutations(range(5), 3):
+            ok &= D[i, j] <= D[i, k] + D[k, j] + 1e-12
+        check("pairwise-triangle", ok)
+    except Exception:
+        failed.append("pairwise-raised")
     return failed
 
 
@@ -202,6 +222,14 @@ MUTATIONS = [
     ("grad.py", "    gw = -0.5 * np.sum(g[None, :] * diff * diff, axis=1)",
      "    gw = -1.0 * np.sum(g[None, :] * diff * diff, axis=1)"),
     ("grad.py", "    return 2.0 * x * g[None, :], gw", "    return x * g[None, :], gw"),
+    ("pairwise.py", "            diff = coef[:, i] - coef[:, j]", "            diff = coef[:, i] + coef[:, j]"),
+    ("pairwise.py", "            dsq = max(float(np.sum(diff * diff / lam[c:])), 0.0)",
+     "            dsq = max(float(np.sum(diff * diff * lam[c:])), 0.0)"),
+    ("pairwise.py", "    c = int(components(n, row_ptr, col_idx).max()) + 1",
+     "    c = int(components(n, row_ptr, col_idx).max())"),                 # keeps a null eigenpair
+    ("pairwise.py", "    r = ge_pcg(n, row_ptr, col_idx, w, V[:, iu], V[:, ju], rtol=rtol)",
+     "    r = ge_pcg(n, row_ptr, col_idx, w, V[:, iu], V[:, iu + 1], rtol=rtol)"),   # wrong partner
+    ("pairwise.py", "            D[i, j] = D[j, i] = np.sqrt(dsq)", "            D[i, j] = np.sqrt(dsq)"),
 ]
 
 # Mutations that do not change the mathematics (self-loops are absent from the
