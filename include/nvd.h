@@ -184,6 +184,29 @@ nvd_status nvd_distances(nvd_graph* g, int32_t k, const double* P,
                          double* d_out, double* X_inout, int64_t ldx,
                          nvd_pair_info* info, void* stream);
 
+/* ---- all pairwise distances among m node vectors --------------------------
+ * D[i][j] = d(v_i, v_j) (section 3.1 distance) for the m columns of V, from
+ * ONE solve with m right-hand sides: X = L^+ V_bar (section 3.2 solve, the
+ * tiles and precision of nvd_distances), R = V_bar - L X its final FP64
+ * residuals, and
+ *     Gt = V_bar^T X + X^T R,   D_ij^2 = Gt_ii + Gt_jj - Gt_ij - Gt_ji,
+ * which equals, by linearity, the quadratic form delta^T x + x^T r of the
+ * pair delta = v_i - v_j: every distance has the accuracy of a pair solved
+ * on its own.
+ * V: device float64 n x m, row-major, leading dimension ld (>= m); 1 <= m
+ *   <= 4096 (NVD_E_UNSUPPORTED above).
+ * opts: as for nvd_distances (NULL: defaults); NVD_WARM_START is rejected.
+ * D: device float64 m x m (ldd >= m): symmetric, zero diagonal.
+ * G: NULL or device float64 m x m (ldg >= m): (Gt + Gt^T) / 2, the Gram
+ *   matrix of the vectors in the L^+ inner product.
+ * info: NULL or host [m]: per-column solve outcome (status as for
+ *   nvd_distances; the return value aggregates NOCONV / BREAKDOWN).
+ * Needs 3 n m + O(m^2) doubles of device scratch, allocated and freed by the
+ * call.  Synchronous with respect to `stream`. */
+nvd_status nvd_pairwise(nvd_graph* g, int32_t m, const double* V, int64_t ld,
+                        const nvd_opts* opts, double* D, int64_t ldd, double* G,
+                        int64_t ldg, nvd_pair_info* info, void* stream);
+
 /* ---- tile autotuner --------------------------------------------------------
  * The tile (pairs per SpMM pass) and the number of lane sub-groups that
  * share each row's neighbours in the Laplacian apply (nl), which

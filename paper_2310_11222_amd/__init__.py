@@ -164,6 +164,27 @@ class Graph:
         infos = [{f: getattr(i, f) for f, _ in PairInfo._fields_} for i in info]
         return d, X, infos
 
+
+    def pairwise(self, V, precision="fp64", rtol=1e-10, inner_rtol=1e-5, max_iter=20000,
+                 max_refine=30, tile_k=0, return_gram=False):
+        """All pairwise distances among the m columns of V (n x m): returns
+        (D m x m, G m x m or None, info list of the m column solves)."""
+        torch = _torch()
+        V = _as_dev64(V, "V")
+        if V.dim() != 2 or V.shape[0] != self.n:
+            raise ValueError(f"V must be ({self.n}, m)")
+        m = V.shape[1]
+        o = opts(precision, rtol, inner_rtol, max_iter, max_refine, tile_k)
+        D = torch.empty(m, m, dtype=torch.float64, device=V.device)
+        G = torch.empty_like(D) if return_gram else None
+        info = (PairInfo * m)()
+        st = load().nvd_pairwise(self._h, m, _ptr(V), V.stride(0), C.byref(o), _ptr(D),
+                                 D.stride(0), _ptr(G), G.stride(0) if G is not None else 0,
+                                 info, _stream())
+        if st not in (_abi.NVD_OK, _abi.NVD_E_NOCONV, _abi.NVD_E_BREAKDOWN):
+            check(st, "nvd_pairwise")
+        infos = [{f: getattr(i, f) for f, _ in PairInfo._fields_} for i in info]
+        return D, G, infos
     def tuning(self, k, precision="mixed"):
         """(tile, neighbour lanes) the autotuner picks for k pairs."""
         t = C.c_int32()

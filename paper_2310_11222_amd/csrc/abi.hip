@@ -82,6 +82,28 @@ __global__ void k_degree_refresh(int n, const int* rp, const double* w64, double
   invd32[i] = (float)inv;
 }
 
+// Solver options: precision, tolerances, limits and tile.
+nvd_status check_solve_opts(const nvd_opts* o) {
+  if (o->precision != NVD_FP64 && o->precision != NVD_MIXED) {
+    set_error("nvd_opts.precision must be NVD_FP64 or NVD_MIXED");
+    return NVD_E_ARG;
+  }
+  if (!(o->rtol > 0.0) || !(o->rtol < 1.0) || !(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0)) {
+    set_error("nvd_opts: rtol and inner_rtol must lie in (0, 1)");
+    return NVD_E_ARG;
+  }
+  if (o->max_iter < 1 || o->max_refine < 1) {
+    set_error("nvd_opts: max_iter and max_refine must be >= 1");
+    return NVD_E_ARG;
+  }
+  const int t = o->tile_k;
+  if (t != 0 && t != 1 && t != 2 && t != 4 && t != 8 && t != 16 && t != 32 && t != 64) {
+    set_error("nvd_opts.tile_k must be 0 or a power of two up to 64");
+    return NVD_E_ARG;
+  }
+  return NVD_OK;
+}
+
 }  // namespace nvd
 
 using namespace nvd;
@@ -226,26 +248,6 @@ nvd_status nvd_project(nvd_graph* h, int32_t k, const double* P, const double* Q
   return NVD_OK;
 }
 
-static nvd_status check_opts(const nvd_opts* o) {
-  if (o->precision != NVD_FP64 && o->precision != NVD_MIXED) {
-    set_error("nvd_opts.precision must be NVD_FP64 or NVD_MIXED");
-    return NVD_E_ARG;
-  }
-  if (!(o->rtol > 0.0) || !(o->rtol < 1.0) || !(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0)) {
-    set_error("nvd_opts: rtol and inner_rtol must lie in (0, 1)");
-    return NVD_E_ARG;
-  }
-  if (o->max_iter < 1 || o->max_refine < 1) {
-    set_error("nvd_opts: max_iter and max_refine must be >= 1");
-    return NVD_E_ARG;
-  }
-  const int t = o->tile_k;
-  if (t != 0 && t != 1 && t != 2 && t != 4 && t != 8 && t != 16 && t != 32 && t != 64) {
-    set_error("nvd_opts.tile_k must be 0 or a power of two up to 64");
-    return NVD_E_ARG;
-  }
-  return NVD_OK;
-}
 
 nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double* Q, int64_t ld,
                          const nvd_opts* opts, double* d_out, double* X, int64_t ldx,
@@ -258,7 +260,7 @@ nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double*
   nvd_opts o;
   nvd_opts_default(&o);
   if (opts) o = *opts;
-  NVD_TRY(check_opts(&o));
+  NVD_TRY(check_solve_opts(&o));
   if ((o.flags & NVD_WARM_START) && !X) {
     set_error("nvd_distances: NVD_WARM_START needs X_inout");
     return NVD_E_ARG;

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kBS) void k_proj_init(int n, long cap, ProjSrc src,
     const int c = (int)(e % T);
     double v = 0.0;
     if (i < n) {
-      v = src.a[i * src.lda + c] - src.b[i * src.ldb + c] - mean_of(m, i, c);
+      v = src.a[i * src.lda + c] - (src.b ? src.b[i * src.ldb + c] : 0.0) - mean_of(m, i, c);
       acc[0][0] += v * v;
       acc[1][0] += v * v * invd[i];
     }

@@ -196,6 +196,8 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
                       nvd_pair_info* info_dev, hipStream_t s);
 nvd_status project_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
                         double* Dbar, int64_t ldd, double* norms, hipStream_t s);
+// Validation of solver options (NVD_E_ARG with a message).
+nvd_status check_solve_opts(const nvd_opts* o);
 int choose_tile(DevGraph* g, int k, int precision, hipStream_t s);
 // One CG iteration (apply + update + direction) on the workspace vectors, timed.
 nvd_status time_cg_iteration(DevGraph* g, int prec, int T, int nl, hipStream_t s, float* ms);

@@ -106,3 +106,4 @@ def test_argument_errors():
     assert lib.nvd_distances(None, 1, None, None, 1, None, None, None, 0, None, None) == abi.NVD_E_ARG
     assert lib.nvd_laplacian_apply(None, 0, 1, None, 1, None, 1, None) == abi.NVD_E_ARG
     assert lib.nvd_opts_default(None) == abi.NVD_E_ARG
+    assert lib.nvd_pairwise(None, 4, None, 4, None, None, 4, None, 0, None, None) == abi.NVD_E_ARG
