@@ -162,6 +162,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--inner-rtol", type=float, default=1e-5)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-pairwise", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 512 MiB device copy first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -275,6 +276,34 @@ def main():
                          f"(true rel. residual 1e-13), {secs:.1f} s single-threaded"}
         log(f"cpu oracle {rate:.3f} distances/s ({secs:.1f}s)")
 
+    # ---- all pairwise distances among the 64 vectors P_j (one 64-column solve)
+    all_pairs = None
+    if not args.no_pairwise:
+        m = P.shape[1]
+        npairs = m * (m - 1) // 2
+        dg.pairwise(P, precision="mixed", rtol=rtol)
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 3))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            D, _, _ = dg.pairwise(P, precision="mixed", rtol=rtol)
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t0) / reps
+        # 8 sampled entries against pairs solved one by one (FP64)
+        iu, ju = np.triu_indices(m, 1)
+        pick = np.random.default_rng(0).choice(npairs, 8, replace=False)
+        ii = torch.as_tensor(iu[pick], device="cuda")
+        jj = torch.as_tensor(ju[pick], device="cuda")
+        dpair, _, _ = dg.distances(P[:, ii].contiguous(), P[:, jj].contiguous(), precision="fp64",
+                                   rtol=1e-10)
+        Dn = D.cpu().numpy()
+        diff = float(np.max(np.abs(Dn[iu[pick], ju[pick]] - dpair.cpu().numpy()) / dpair.cpu().numpy()))
+        all_pairs = {"workload": "ba_n1e6_m3_unit_64_vectors_all_pairs", "vectors": m,
+                     "pairs": npairs, "value": round(npairs / tp, 1), "unit": "distances/s",
+                     "ms_per_call": round(tp * 1e3, 3), "precision": "mixed",
+                     "max_rel_diff_vs_pair_solves": diff}
+        log(f"all pairs: {all_pairs}")
+
     batched = None
     if not args.no_batched:
         dg.close()
@@ -304,6 +333,7 @@ def main():
                       "ms_per_step": round(t64 * 1e3, 3)},
         "accuracy": acc,
         "batched": batched,
+        "all_pairs": all_pairs,
         "iters_mean": float(np.mean(iters_mixed)),
         "refine_mean": float(np.mean(refine)),
         "setup_s": round(setup_s, 3),

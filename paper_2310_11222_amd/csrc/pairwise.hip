@@ -15,7 +15,7 @@
 //
 // Gt is an FP64 contraction over the n rows: 64 x 64 output tiles, split over
 // row slices so that small m still fills the GPU; the slices' partial tiles
-// are added in slice order (results repeat bit for bit).
+// are added in a fixed order (results repeat bit for bit).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -105,14 +105,30 @@ __global__ __launch_bounds__(256) void k_gram(int n, int m, const double* __rest
   }
 }
 
-// Gt = sum of the S partial tiles, in slice order.
-__global__ void k_gram_sum(int m, int S, const double* __restrict__ part, double* __restrict__ Gt) {
+// Gt = sum of the S partial tiles in two fixed-order levels: group y of
+// blockIdx.y adds slices [y*per, (y+1)*per) into part2[y], then k_gram_sum2
+// adds the groups in order.  Consecutive threads take consecutive entries,
+// so every load is coalesced.
+constexpr int kSumGroups = 64;
+__global__ void k_gram_sum1(int m, int S, const double* __restrict__ part, double* __restrict__ part2) {
   const long mm = (long)m * m;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < mm; e += (long)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int s = 0; s < S; ++s) acc += part[(size_t)s * mm + e];
-    Gt[e] = acc;
-  }
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mm) return;
+  const int per = (S + kSumGroups - 1) / kSumGroups;
+  const int s0 = blockIdx.y * per;
+  const int s1 = min(S, s0 + per);
+  double acc = 0.0;
+  for (int s = s0; s < s1; ++s) acc += part[(size_t)s * mm + e];
+  part2[(size_t)blockIdx.y * mm + e] = acc;
+}
+
+__global__ void k_gram_sum2(int m, const double* __restrict__ part2, double* __restrict__ Gt) {
+  const long mm = (long)m * m;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mm) return;
+  double acc = 0.0;
+  for (int y = 0; y < kSumGroups; ++y) acc += part2[(size_t)y * mm + e];
+  Gt[e] = acc;
 }
 
 // D_ij = sqrt(max(Gt_ii + Gt_jj - Gt_ij - Gt_ji, 0)), D_ii = 0; optionally the
@@ -173,13 +189,14 @@ extern "C" nvd_status nvd_pairwise(nvd_graph* h, int32_t m, const double* V, int
   if (S < 1) S = 1;
   // device scratch, freed on return
   double* buf = nullptr;
-  const size_t nbuf = 3 * nm + (size_t)S * m * m + (size_t)m * m + kMaxTile;
+  const size_t nbuf = 3 * nm + (size_t)(S + kSumGroups + 1) * m * m + kMaxTile;
   NVD_HIP(hipMalloc((void**)&buf, nbuf * sizeof(double)));
   double* Vb = buf;
   double* X = Vb + nm;
   double* R = X + nm;
   double* part = R + nm;
-  double* Gt = part + (size_t)S * m * m;
+  double* part2 = part + (size_t)S * m * m;
+  double* Gt = part2 + (size_t)kSumGroups * m * m;
   double* dscratch = Gt + (size_t)m * m;
   SolveParams sp{};
   sp.precision = o.precision;
@@ -220,7 +237,9 @@ extern "C" nvd_status nvd_pairwise(nvd_graph* h, int32_t m, const double* V, int
   if (st == NVD_OK) {
     k_gram<<<dim3(ntiles, S), 256, 0, s>>>(n, m, Vb, X, R, rows_per_slice, tiles_1d, part);
     const int g2 = (int)std::min<long>(1024, ((long)m * m + 255) / 256);
-    k_gram_sum<<<std::max(g2, 1), 256, 0, s>>>(m, S, part, Gt);
+    const int ge = (int)(((long)m * m + 255) / 256);
+    k_gram_sum1<<<dim3(ge, kSumGroups), 256, 0, s>>>(m, S, part, part2);
+    k_gram_sum2<<<ge, 256, 0, s>>>(m, part2, Gt);
     k_pdist<<<std::max(g2, 1), 256, 0, s>>>(m, Gt, D, ldd, G, ldg);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
