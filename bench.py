@@ -135,6 +135,37 @@ def bench_batched(steps, warmup):
     return res
 
 
+def bench_density():
+    """Section 4.2 density sweep: |V| = 10^4, average degree 1..64 on ER, BA,
+    WS and SBM, 8 pairs per graph, mixed precision to 1e-8 (the time of one
+    call after a warm-up call, and the largest CG iteration count)."""
+    import torch
+    import paper_2310_11222_amd as nvd
+    from nvdgen import density_graph, DENSITY_MODELS, DENSITY_DEGREES
+    out = {}
+    for model in DENSITY_MODELS:
+        rows = []
+        for d in DENSITY_DEGREES:
+            g, P, Q = density_graph(model, d)
+            dg = nvd.Graph(g.row_ptr, g.col_idx, None)
+            Pd = torch.as_tensor(P).cuda()
+            Qd = torch.as_tensor(Q).cuda()
+            dg.distances(Pd, Qd, precision="mixed", rtol=1e-8)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, info = dg.distances(Pd, Qd, precision="mixed", rtol=1e-8)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            rows.append({"avg_degree": d, "ms_per_8": round(t * 1e3, 3),
+                         "iters": max(i["iters"] for i in info),
+                         "components": dg.stats()["n_comp"]})
+            dg.close()
+        out[model] = rows
+    log("density sweep (ms per 8 distances): " +
+        json.dumps({m: [r["ms_per_8"] for r in v] for m, v in out.items()}))
+    return {"workload": "density_sweep_n1e4_deg1_to_64", "models": out}
+
+
 def cpu_baseline(w, pairs):
     """The oracle (FP64 Jacobi-PCG route, unmodified defaults) on `pairs`
     pairs of the same workload, single-threaded."""
@@ -163,6 +194,7 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-5)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-pairwise", action="store_true")
+    ap.add_argument("--no-density", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 512 MiB device copy first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -304,6 +336,8 @@ def main():
                      "max_rel_diff_vs_pair_solves": diff}
         log(f"all pairs: {all_pairs}")
 
+    density = None if args.no_density else bench_density()
+
     batched = None
     if not args.no_batched:
         dg.close()
@@ -334,6 +368,7 @@ def main():
         "accuracy": acc,
         "batched": batched,
         "all_pairs": all_pairs,
+        "density_sweep": density,
         "iters_mean": float(np.mean(iters_mixed)),
         "refine_mean": float(np.mean(refine)),
         "setup_s": round(setup_s, 3),

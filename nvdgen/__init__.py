@@ -6,4 +6,5 @@ GPU library's tests and benchmarks.
 """
 from .graphs import *  # noqa: F401,F403
 from .vectors import *  # noqa: F401,F403
-from .configs import Workload, workload, ws_connected, seeds  # noqa: F401
+from .configs import (Workload, workload, ws_connected, seeds, density_graph,  # noqa: F401
+                      DENSITY_MODELS, DENSITY_DEGREES, DENSITY_N)

@@ -21,10 +21,11 @@ from typing import List, Optional
 import numpy as np
 
 from .graphs import (Graph, barabasi_albert, watts_strogatz, is_connected,
-                     configuration_model_powerlaw, giant_component)
+                     configuration_model_powerlaw, giant_component, erdos_renyi, sbm_sparse)
 from .vectors import (sparse_support_pairs, uniform_weights, lognormal_weights)
 
-__all__ = ["Workload", "workload", "ws_connected", "seeds"]
+__all__ = ["Workload", "workload", "ws_connected", "seeds", "density_graph", "DENSITY_MODELS",
+           "DENSITY_DEGREES", "DENSITY_N"]
 
 
 def seeds(c):
@@ -114,3 +115,43 @@ def workload(c: int, scale: float = 1.0, k: Optional[int] = None,
         return Workload("cm_pl2.5_n1e7_k16", [g], [P], [Q], 1e-8, "mixed",
                         notes={"n_before_gc": n0, "kmax": kmax})
     raise ValueError(c)
+
+
+# ---------------------------------------------------------------------------
+# Density sweep (section 4.2, "Runtimes (Density)"): |V| = 10,000 and the
+# average degree from 1 to 64 on the four models of section 4.1.2, with
+# roughly the same number of edges across models at each degree.
+# ---------------------------------------------------------------------------
+DENSITY_N = 10_000
+DENSITY_MODELS = ("er", "ba", "ws", "sbm")
+DENSITY_DEGREES = (1, 2, 4, 8, 16, 32, 64)
+
+
+def density_graph(model: str, avg_degree: int, n: int = DENSITY_N, k: int = 8):
+    """One graph of the density sweep and k vector pairs on it.
+
+    * er:  G(n, m) with m = n * d / 2 edges (disconnected at low d).
+    * ba:  each new node attaches to max(1, round(d / 2)) earlier nodes
+           (average degree ~2 at d = 1: the model cannot go lower).
+    * ws:  ring with k' = max(2, 2 round(d / 2)) neighbours, rewiring 0.1.
+    * sbm: 10 equal groups, p_out = p_in / 10, p_in set for expected degree d.
+    Vectors: uniform[0, 1) on independent 10% supports.  Seeds:
+    SeedSequence([2310, 11222, 42, model index, d]) children 0 (graph) and 1
+    (pairs)."""
+    mi = DENSITY_MODELS.index(model)
+    sg, sp = np.random.SeedSequence([2310, 11222, 42, mi, int(avg_degree)]).spawn(2)
+    rg = _rng(sg)
+    d = float(avg_degree)
+    if model == "er":
+        g = erdos_renyi(n, int(round(n * d / 2)), rg)
+    elif model == "ba":
+        g = barabasi_albert(n, max(1, int(round(d / 2))), rg)
+    elif model == "ws":
+        g = watts_strogatz(n, max(2, 2 * int(round(d / 2))), 0.1, rg)
+    else:
+        groups = 10
+        s = n // groups
+        p_in = d / ((s - 1) + 0.1 * (n - s))
+        g = sbm_sparse([s] * groups, p_in, p_in / 10.0, rg)
+    P, Q = sparse_support_pairs(g.n, k, 0.10, _rng(sp))
+    return g, P, Q

@@ -21,7 +21,7 @@ from scipy.sparse.csgraph import connected_components
 
 __all__ = [
     "Graph", "to_csr", "barabasi_albert", "watts_strogatz", "erdos_renyi",
-    "stochastic_block_model", "configuration_model_powerlaw", "giant_component",
+    "stochastic_block_model", "sbm_sparse", "configuration_model_powerlaw", "giant_component",
     "path_graph", "cycle_graph", "complete_graph", "star_graph",
     "complete_bipartite", "random_tree", "grid_graph", "is_connected",
 ]
@@ -248,6 +248,32 @@ def stochastic_block_model(sizes, p_in, p_out, rng):
     prob = np.where(block[iu] == block[iv], p_in, p_out)
     keep = rng.random(iu.size) < prob
     return Graph(n, iu[keep], iv[keep])
+
+
+def sbm_sparse(sizes, p_in, p_out, rng):
+    """SBM with the same distribution as ``stochastic_block_model`` (every
+    pair an independent Bernoulli draw) for larger n: per block pair, the edge
+    count is drawn from the binomial and that many distinct pairs uniformly."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    eu, ev = [], []
+    for a in range(sizes.size):
+        for b in range(a, sizes.size):
+            if a == b:
+                s = int(sizes[a])
+                npairs = s * (s - 1) // 2
+                cnt = rng.binomial(npairs, p_in)
+                pick = rng.choice(npairs, cnt, replace=False)
+                iu, iv = np.triu_indices(s, 1)
+                eu.append(iu[pick] + offs[a])
+                ev.append(iv[pick] + offs[a])
+            else:
+                sa, sb = int(sizes[a]), int(sizes[b])
+                cnt = rng.binomial(sa * sb, p_out)
+                pick = rng.choice(sa * sb, cnt, replace=False)
+                eu.append(pick // sb + offs[a])
+                ev.append(pick % sb + offs[b])
+    return Graph(int(offs[-1]), np.concatenate(eu), np.concatenate(ev))
 
 
 # ---------------------------------------------------------------------------

@@ -90,3 +90,40 @@ def test_workloads_small_scale():
     # determinism
     again = workload(1)
     assert np.array_equal(again.P[0], w1.P[0])
+
+
+def test_density_sweep_graphs():
+    """Section 4.2 density sweep recipe: n = 10^4, average degree on target
+    (BA and WS cannot go below 2), seeded (same call, same graph)."""
+    from nvdgen import density_graph, DENSITY_MODELS, DENSITY_N
+    for model in DENSITY_MODELS:
+        for d in (1, 4, 16):
+            g, P, Q = density_graph(model, d)
+            assert g.n == DENSITY_N and P.shape == (DENSITY_N, 8) and Q.shape == P.shape
+            avg = 2 * g.num_edges / g.n
+            want = max(d, 2) if model in ("ba", "ws") else d
+            assert abs(avg - want) <= 0.05 * want + 0.05, (model, d, avg)
+            assert np.all(g.eu < g.ev) or np.all(g.eu != g.ev)
+    g1, P1, _ = density_graph("sbm", 8)
+    g2, P2, _ = density_graph("sbm", 8)
+    assert np.array_equal(g1.row_ptr, g2.row_ptr) and np.array_equal(g1.col_idx, g2.col_idx)
+    assert np.array_equal(P1, P2)
+
+
+def test_sbm_sparse_edge_counts():
+    """The sparse SBM draw keeps the Bernoulli model's expected counts: inside
+    and across blocks, within 5 standard deviations."""
+    from nvdgen import sbm_sparse
+    rng = np.random.default_rng(3)
+    sizes = [300, 500, 200]
+    p_in, p_out = 0.05, 0.004
+    g = sbm_sparse(sizes, p_in, p_out, rng)
+    blk = np.repeat(np.arange(3), sizes)
+    same = blk[g.eu] == blk[g.ev]
+    n_in = sum(s * (s - 1) // 2 for s in sizes)
+    n_out = (sum(sizes) ** 2 - sum(s * s for s in sizes)) // 2
+    for cnt, npairs, p in ((same.sum(), n_in, p_in), ((~same).sum(), n_out, p_out)):
+        mu, sd = npairs * p, np.sqrt(npairs * p * (1 - p))
+        assert abs(cnt - mu) <= 5 * sd, (cnt, mu, sd)
+    keys = np.minimum(g.eu, g.ev) * g.n + np.maximum(g.eu, g.ev)
+    assert np.unique(keys).size == keys.size and np.all(g.eu != g.ev)
