@@ -213,8 +213,8 @@ MUTATIONS = [
      "        x[lev] = x[parent[lev]] - f[lev] / pw[lev, None]"),
     ("tree.py", "    dsq = np.sum(f[nonroot] ** 2 / pw[nonroot, None], axis=0)",
      "    dsq = np.sum(f[nonroot] ** 2 * pw[nonroot, None], axis=0)"),
-    ("cycle.py", "    lam = w * (2.0 - 2.0 * np.cos(2.0 * np.pi * kk / n))",
-     "    lam = w * (2.0 - 2.0 * np.cos(np.pi * kk / n))"),
+    ("cycle.py", "    lam = 4.0 * w * np.sin(np.pi * kk / n) ** 2",
+     "    lam = 4.0 * w * np.sin(2.0 * np.pi * kk / n) ** 2"),
     ("cycle.py", "    dsq = np.sum(np.abs(dh[1:]) ** 2 / lam[:, None], axis=0) / n",
      "    dsq = np.sum(np.abs(dh[1:]) ** 2 / lam[:, None], axis=0) / (n - 1)"),
     ("grad.py", "    gw = -0.5 * np.sum(g[None, :] * diff * diff, axis=1)",

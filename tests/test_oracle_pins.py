@@ -178,6 +178,20 @@ def test_pcg_matches_exact_cycle_high_condition():
     np.testing.assert_allclose(c["d"], e["d"], rtol=1e-10)
 
 
+def test_cycle_closed_form_keeps_digits_at_large_n():
+    """At n = 2e5 the smallest cycle eigenvalue is ~1e-9; the closed form must
+    not lose it to cancellation (2 - 2 cos does, by ~3e-8 on d).  Against the
+    grounded sparse solve of the same cycle."""
+    n = 200_000
+    g = cycle_graph(n)
+    rng = np.random.default_rng(2)
+    P = np.where(rng.random((n, 3)) < 0.01, rng.random((n, 3)), 0.0)
+    Q = np.where(rng.random((n, 3)) < 0.01, rng.random((n, 3)), 0.0)
+    e = oracle.ge_cycle(n, P, Q)
+    gr = oracle.ge_grounded(n, g.row_ptr, g.col_idx, None, P, Q, sparse=True)
+    np.testing.assert_allclose(e["d"], gr["d"], rtol=5e-9)
+
+
 def test_foster_theorem():
     """sum_e w_e R_e = n - c (Foster's theorem)."""
     rng = np.random.default_rng(8)
