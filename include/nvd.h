@@ -81,8 +81,13 @@ enum { NVD_DT_F64 = 0, NVD_DT_F32 = 1 };
 /* nvd_opts.flags */
 enum {
   NVD_WARM_START = 1u,      /* X_inout holds a starting guess on entry */
-  NVD_BATCH_PERSISTENT = 2u /* nvd_batch_distances: the single persistent
+  NVD_BATCH_PERSISTENT = 2u,/* nvd_batch_distances: the single persistent
                                launch instead of the sweep solver */
+  NVD_PRECOND_TREE = 4u     /* nvd_distances / nvd_pairwise: precondition CG
+                               with a spanning forest of the graph (exact
+                               tree solve, section 3.2 tree preconditioners)
+                               instead of the Jacobi diagonal; for very sparse
+                               graphs.  Not for batches. */
 };
 
 typedef struct nvd_graph nvd_graph;
@@ -102,7 +107,7 @@ typedef struct nvd_opts {
   int32_t max_refine;  /* MIXED: outer refinement steps; default 30 */
   int32_t tile_k;      /* columns per SpMM pass: 1,2,4,8,16,32,64; 0 = the
                           library's autotuned choice */
-  uint32_t flags;      /* NVD_WARM_START, NVD_BATCH_PERSISTENT */
+  uint32_t flags;      /* NVD_WARM_START, NVD_BATCH_PERSISTENT, NVD_PRECOND_TREE */
 } nvd_opts;
 
 typedef struct nvd_pair_info {

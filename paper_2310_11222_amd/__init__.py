@@ -50,7 +50,7 @@ def _as_dev64(M, name):
 
 
 def opts(precision="fp64", rtol=1e-10, inner_rtol=1e-5, max_iter=20000, max_refine=30,
-         tile_k=0, warm_start=False) -> NvdOpts:
+         tile_k=0, warm_start=False, precond="jacobi") -> NvdOpts:
     o = NvdOpts()
     check(load().nvd_opts_default(C.byref(o)))
     o.precision = {"fp64": NVD_FP64, "mixed": NVD_MIXED}[precision]
@@ -60,6 +60,10 @@ def opts(precision="fp64", rtol=1e-10, inner_rtol=1e-5, max_iter=20000, max_refi
     o.max_refine = max_refine
     o.tile_k = tile_k
     o.flags = NVD_WARM_START if warm_start else 0
+    if precond == "tree":
+        o.flags |= _abi.NVD_PRECOND_TREE
+    elif precond != "jacobi":
+        raise ValueError("precond must be 'jacobi' or 'tree'")
     return o
 
 
@@ -140,7 +144,8 @@ class Graph:
 
     # -- distances ----------------------------------------------------------
     def distances(self, P, Q, precision="fp64", rtol=1e-10, inner_rtol=1e-5, max_iter=20000,
-                  max_refine=30, tile_k=0, return_x=False, X0=None, raise_on_noconv=False):
+                  max_refine=30, tile_k=0, return_x=False, X0=None, raise_on_noconv=False,
+                  precond="jacobi"):
         """Returns (d, X or None, info list).  P, Q: (n, k) or (n,) float64."""
         torch = _torch()
         P = _as_dev64(P, "P")
@@ -148,7 +153,7 @@ class Graph:
         if P.shape != Q.shape or P.shape[0] != self.n:
             raise ValueError(f"P, Q must both be ({self.n}, k)")
         k = P.shape[1]
-        o = opts(precision, rtol, inner_rtol, max_iter, max_refine, tile_k, X0 is not None)
+        o = opts(precision, rtol, inner_rtol, max_iter, max_refine, tile_k, X0 is not None, precond)
         d = torch.empty(k, dtype=torch.float64, device=P.device)
         X = None
         if return_x or X0 is not None:
@@ -166,7 +171,7 @@ class Graph:
 
 
     def pairwise(self, V, precision="fp64", rtol=1e-10, inner_rtol=1e-5, max_iter=20000,
-                 max_refine=30, tile_k=0, return_gram=False):
+                 max_refine=30, tile_k=0, return_gram=False, precond="jacobi"):
         """All pairwise distances among the m columns of V (n x m): returns
         (D m x m, G m x m or None, info list of the m column solves)."""
         torch = _torch()
@@ -174,7 +179,7 @@ class Graph:
         if V.dim() != 2 or V.shape[0] != self.n:
             raise ValueError(f"V must be ({self.n}, m)")
         m = V.shape[1]
-        o = opts(precision, rtol, inner_rtol, max_iter, max_refine, tile_k)
+        o = opts(precision, rtol, inner_rtol, max_iter, max_refine, tile_k, precond=precond)
         D = torch.empty(m, m, dtype=torch.float64, device=V.device)
         G = torch.empty_like(D) if return_gram else None
         info = (PairInfo * m)()

@@ -14,6 +14,7 @@ NVD_FP64, NVD_MIXED = 0, 1
 NVD_DT_F64, NVD_DT_F32 = 0, 1
 NVD_WARM_START = 1
 NVD_BATCH_PERSISTENT = 2
+NVD_PRECOND_TREE = 4
 
 
 class NvdOpts(C.Structure):

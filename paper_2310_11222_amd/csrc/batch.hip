@@ -53,8 +53,6 @@ struct BatchArgs {
   const int* ci;
   const double* w64;
   const float* w32;
-  const double* deg64;
-  const float* deg32;
   const double* invd64;
   const float* invd32;
   const int* long_rows;
@@ -247,20 +245,16 @@ __device__ __noinline__ void block_spmm(const BatchArgs& a, const BGraph& gd, in
   const int* ci = a.ci + gd.nnz_off;
   const bool unit = !gd.weighted;
   const V* wv = nullptr;
-  const V* dgv = nullptr;
-  if constexpr (sizeof(V) == 8) {
+  if constexpr (sizeof(V) == 8)
     wv = reinterpret_cast<const V*>(a.w64 + gd.nnz_off);
-    dgv = reinterpret_cast<const V*>(a.deg64 + gd.v_off / T);
-  } else {
+  else
     wv = reinterpret_cast<const V*>(a.w32 + gd.nnz_off);
-    dgv = reinterpret_cast<const V*>(a.deg32 + gd.v_off / T);
-  }
   constexpr int ROWS_PER_WAVE = RW * R;
   constexpr int ROWS_PER_STEP = (BBS / 64) * ROWS_PER_WAVE;
   for (int base = lo; base < hi; base += ROWS_PER_STEP) {
     int row[R], rs[R], deg[R];
     bool mine[R];
-    V own[R], dg[R];
+    V own[R];
     double bb[R];
     int maxdeg = 0;
 #pragma unroll
@@ -277,7 +271,6 @@ __device__ __noinline__ void block_spmm(const BatchArgs& a, const BGraph& gd, in
     for (int r = 0; r < R; ++r) {
       mine[r] = deg[r] >= 0 && deg[r] <= kLongRow;
       own[r] = mine[r] ? vld<SH>(&x[(long)row[r] * T + c]) : (V)0;
-      dg[r] = mine[r] ? (unit ? (V)deg[r] : dgv[row[r]]) : (V)0;
       bb[r] = 0.0;
       if constexpr (EPI == EPI_RESID) bb[r] = mine[r] ? b[(long)row[r] * T + c] : 0.0;
       if (!mine[r]) deg[r] = 0;
@@ -309,13 +302,15 @@ __device__ __noinline__ void block_spmm(const BatchArgs& a, const BGraph& gd, in
             const int idx = j + NL * (m0 + m);
             const int col = __shfl(myc[r], idx, G);
             ww[r][m] = __shfl(myw[r], idx, G);
-            xv[r][m] = idx < cnt[r] ? vld<SH>(&x[(long)col * T + c]) : (V)0;
+            // a slot past the row's end takes the row's own value: its
+            // difference, whatever its weight, is zero
+            xv[r][m] = idx < cnt[r] ? vld<SH>(&x[(long)col * T + c]) : own[r];
           }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
-          for (int m = 0; m < MB; ++m) sum[r] += ww[r][m] * xv[r][m];
+          for (int m = 0; m < MB; ++m) sum[r] += ww[r][m] * (own[r] - xv[r][m]);
       }
     }
 #pragma unroll
@@ -327,7 +322,7 @@ __device__ __noinline__ void block_spmm(const BatchArgs& a, const BGraph& gd, in
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (!mine[r]) continue;
-        const V yv = dg[r] * own[r] - sum[r];
+        const V yv = sum[r];
         if constexpr (EPI == EPI_CG) {
           y[(long)row[r] * T + c] = yv;
           acc[0][0] += (double)own[r] * (double)yv;
@@ -349,15 +344,15 @@ __device__ __noinline__ void block_spmm(const BatchArgs& a, const BGraph& gd, in
     const int row = lr[q];
     if (row < lo || row >= hi) continue;      // uniform across the block
     const int rs = rp[row], re = rp[row + 1];
+    const V xr = vld<SH>(&x[(long)row * T + t % T]);
     V sum = (V)0;
     for (int e = rs + t / T; e < re; e += NJ)
-      sum += (unit ? (V)1 : wv[e]) * vld<SH>(&x[(long)ci[e] * T + t % T]);
+      sum += (unit ? (V)1 : wv[e]) * (xr - vld<SH>(&x[(long)ci[e] * T + t % T]));
     double part[1][1] = {{(double)sum}};
     block_reduce_cols<BBS, 1, 1>(part, T, sh_long);
     if (t < T) {
       const V own = vld<SH>(&x[(long)row * T + t]);
-      const V dg = unit ? (V)(re - rs) : dgv[row];
-      const V yv = dg * own - (V)sh_long[t];
+      const V yv = (V)sh_long[t];
       if constexpr (EPI == EPI_CG) {
         y[(long)row * T + t] = yv;
         acc[0][0] += (double)own * (double)yv;
@@ -884,8 +879,6 @@ nvd_status nvd_batch_create(int32_t G, nvd_graph* const* graphs, void* stream, n
     chk(balloc(b, &b->w64, b->tot_nnz));
     chk(balloc(b, &b->w32, b->tot_nnz));
   }
-  chk(balloc(b, &b->deg64, b->tot_n));
-  chk(balloc(b, &b->deg32, b->tot_n));
   chk(balloc(b, &b->invd64, b->tot_n));
   chk(balloc(b, &b->invd32, b->tot_n));
   chk(balloc(b, &b->long_rows, b->tot_long));
@@ -907,8 +900,6 @@ nvd_status nvd_batch_create(int32_t G, nvd_graph* const* graphs, void* stream, n
         cp(b->w32 + b->nnz_off[i], g->w32, sizeof(float) * g->nnz);
       }
     }
-    cp(b->deg64 + b->node_off[i], g->deg64, sizeof(double) * g->n);
-    cp(b->deg32 + b->node_off[i], g->deg32, sizeof(float) * g->n);
     cp(b->invd64 + b->node_off[i], g->invd64, sizeof(double) * g->n);
     cp(b->invd32 + b->node_off[i], g->invd32, sizeof(float) * g->n);
     for (int r = 0; r < g->n; ++r)
@@ -1101,8 +1092,6 @@ static nvd_status run_batch(nvd_batch* b, const std::vector<int>& ks, const doub
   a.ci = b->ci;
   a.w64 = b->w64;
   a.w32 = b->w32;
-  a.deg64 = b->deg64;
-  a.deg32 = b->deg32;
   a.invd64 = b->invd64;
   a.invd32 = b->invd32;
   a.long_rows = b->long_rows;
@@ -1258,6 +1247,10 @@ extern "C" nvd_status nvd_batch_distances(nvd_batch* b, const int32_t* k_per_gra
   if (o.precision != NVD_FP64 && o.precision != NVD_MIXED) {
     set_error("nvd_batch_distances: bad precision");
     return NVD_E_ARG;
+  }
+  if (o.flags & NVD_PRECOND_TREE) {
+    set_error("nvd_batch_distances: the tree preconditioner is not available for batches");
+    return NVD_E_UNSUPPORTED;
   }
   if (!(o.rtol > 0 && o.rtol < 1 && o.inner_rtol > 0 && o.inner_rtol < 1) || o.max_iter < 1 ||
       o.max_refine < 1) {

@@ -23,8 +23,6 @@ struct nvd_batch {
   int* ci = nullptr;
   double* w64 = nullptr;
   float* w32 = nullptr;
-  double* deg64 = nullptr;
-  float* deg32 = nullptr;
   double* invd64 = nullptr;
   float* invd32 = nullptr;
   int* long_rows = nullptr;
@@ -86,7 +84,7 @@ static void batch_drop_graph(nvd_batch* b) {
 static void batch_free(nvd_batch* b) {
   batch_drop_graph(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  void* ptrs[] = {b->rp, b->ci, b->w64, b->w32, b->deg64, b->deg32, b->invd64, b->invd32,
+  void* ptrs[] = {b->rp, b->ci, b->w64, b->w32, b->invd64, b->invd32,
                   b->long_rows, b->b64, b->x64, b->r64, b->cv, b->rv, b->pv, b->qv, b->gd,
                   b->plan_buf, b->ctr, b->pool_next, b->err, b->part, b->info, b->trace,
                   b->ch_buf, b->sg_dev, b->spart, b->sstate};

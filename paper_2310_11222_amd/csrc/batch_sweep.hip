@@ -63,8 +63,6 @@ struct SArgs {
   const int* ci;
   const double* w64;
   const float* w32;
-  const double* deg64;
-  const float* deg32;
   const double* invd64;
   const float* invd32;
   double* b64;
@@ -338,14 +336,10 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
     const int* ci = a.ci + sg.nnz_off;
     const bool unit = !sg.weighted;
     const V* wv;
-    const V* dgv;
-    if constexpr (sizeof(V) == 8) {
+    if constexpr (sizeof(V) == 8)
       wv = reinterpret_cast<const V*>(a.w64 + sg.nnz_off);
-      dgv = reinterpret_cast<const V*>(a.deg64 + sg.node_off);
-    } else {
+    else
       wv = reinterpret_cast<const V*>(a.w32 + sg.nnz_off);
-      dgv = reinterpret_cast<const V*>(a.deg32 + sg.node_off);
-    }
     const V* x = xall + sg.node_off * T;
     V* y = yall + sg.node_off * T;
     const double* b = a.b64 + sg.node_off * T;
@@ -357,10 +351,11 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
     auto ldrow = [&](int row, int vi, V (&o)[VW]) {
       unpack<V, VW>(reinterpret_cast<const VV*>(x + (long)row * T)[vi], o);
     };
-    auto epilogue = [&](int row, int vi, const V (&sum)[VW], const V (&own)[VW], V dg) {
+    // sum = (L x) of the row, accumulated as edge differences w (x_v - x_u)
+    auto epilogue = [&](int row, int vi, const V (&sum)[VW], const V (&own)[VW]) {
       V yv[VW];
 #pragma unroll
-      for (int v = 0; v < VW; ++v) yv[v] = dg * own[v] - sum[v];
+      for (int v = 0; v < VW; ++v) yv[v] = sum[v];
       VV* yp = reinterpret_cast<VV*>(y + (long)row * T) + vi;
       if constexpr (EPI == EPI_CG) {
         __builtin_nontemporal_store(pack<V, VW>(yv), yp);
@@ -399,7 +394,6 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
         }
         V own[VW];
         ldrow(mine ? row : lo, cv, own);
-        const V dg = mine ? (unit ? (V)deg : dgv[row]) : (V)0;
         V sum[VW];
 #pragma unroll
         for (int v = 0; v < VW; ++v) sum[v] = (V)0;
@@ -426,17 +420,18 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
             V xs[VW];
             unpack<V, VW>(xv[u], xs);
 #pragma unroll
-            for (int v = 0; v < VW; ++v) sum[v] += wt[u] * xs[v];
+            for (int v = 0; v < VW; ++v) sum[v] += wt[u] * (own[v] - xs[v]);
           }
         }
-        if (mine) epilogue(row, cv, sum, own, dg);
+        if (mine) epilogue(row, cv, sum, own);
       }
     } else {
       // one long row: the whole block, SBS/L neighbour slots
       const int row = lo;
       const int rs = rp[row], re = rp[row + 1];
       constexpr int NJ = SBS / L;
-      V sum[VW];
+      V sum[VW], xr[VW];
+      ldrow(row, cv, xr);
 #pragma unroll
       for (int v = 0; v < VW; ++v) sum[v] = (V)0;
       for (int e = rs + t / L; e < re; e += NJ) {
@@ -444,7 +439,7 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
         ldrow(ci[e], cv, xs);
         const V wt = unit ? (V)1 : wv[e];
 #pragma unroll
-        for (int v = 0; v < VW; ++v) sum[v] += wt * xs[v];
+        for (int v = 0; v < VW; ++v) sum[v] += wt * (xr[v] - xs[v]);
       }
       double pr[1][VW];
 #pragma unroll
@@ -455,7 +450,7 @@ __global__ __launch_bounds__(SBS) void ks_spmm(SArgs a) {
 #pragma unroll
         for (int v = 0; v < VW; ++v) tot[v] = (V)sh[t * VW + v];
         ldrow(row, t, own);
-        epilogue(row, t, tot, own, unit ? (V)(re - rs) : dgv[row]);
+        epilogue(row, t, tot, own);
       }
       __syncthreads();
     }
@@ -941,8 +936,6 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
   a.ci = b->ci;
   a.w64 = b->w64;
   a.w32 = b->w32;
-  a.deg64 = b->deg64;
-  a.deg32 = b->deg32;
   a.invd64 = b->invd64;
   a.invd32 = b->invd32;
   a.b64 = b->b64;

@@ -176,8 +176,10 @@ __device__ __forceinline__ void invd_of(const V* __restrict__ invd, int n, long 
 }
 
 // x += alpha p; r -= alpha q; rho' = r^T D^-1 r; ||r||^2.  The grid's last
-// block forms beta and retires converged columns.
-template <typename V, int T>
+// block forms beta and retires converged columns.  TREE (spanning-tree
+// preconditioner): ||r||^2 and retirement only; rho' = r^T z and beta follow
+// once z = L_T^+ r is known (k_rz).
+template <typename V, int T, bool TREE = false>
 __global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__ x,
                                                 V* __restrict__ r, const V* __restrict__ p,
                                                 const V* __restrict__ q,
@@ -206,13 +208,13 @@ __global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__
     const V* ps = reinterpret_cast<const V*>(&pv);
     const V* qs = reinterpret_cast<const V*>(&qv);
     V iv[N];
-    invd_of<V, T>(invd, n, i, iv);
+    if constexpr (!TREE) invd_of<V, T>(invd, n, i, iv);
 #pragma unroll
     for (int v = 0; v < N; ++v) {
       xs[v] += al[v] * ps[v];
       rs[v] -= al[v] * qs[v];
       const double rd = (double)rs[v];
-      acc[0][v] += rd * rd * (double)iv[v];
+      if constexpr (!TREE) acc[0][v] += rd * rd * (double)iv[v];
       acc[1][v] += rd * rd;
     }
     reinterpret_cast<VT*>(x)[i] = xv;
@@ -239,6 +241,8 @@ __global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__
         cs->active[t] = 0;
         cs->status[t] = kStNoconv;
         cs->oactive[t] = 0;
+      } else if (TREE) {
+        // beta from r^T z in k_rz
       } else if (!(rz > 0.0) || !isfinite(rz)) {
         cs->active[t] = 0;
         cs->status[t] = kStBreak;
@@ -285,6 +289,89 @@ __global__ __launch_bounds__(kBS) void k_direction(int n, long cap, V* __restric
     invd_of<V, T>(invd, n, i, iv);
 #pragma unroll
     for (int v = 0; v < N; ++v) ps[v] = rs[v] * iv[v] + be[v] * ps[v];
+    reinterpret_cast<VT*>(p)[i] = pv;
+  }
+}
+
+// Spanning-tree preconditioner: rho = r^T z with z = L_T^+ r.
+//   MODE 0 (start of a CG run): rho = r^T z (columns with r^T z <= 0, i.e.
+//           r = 0, are retired);
+//   MODE 1 (each iteration): beta = rho' / rho, rho = rho'.  r^T z >= 0
+//           holds exactly, but once r is at rounding level the computed
+//           value can fall to zero or below (more so with a preconditioner
+//           as close to L^+ as a tree is on tree-like graphs): such a column
+//           is retired as stalled, and the true-residual check that follows
+//           every CG run decides whether it converged.  Only a value that
+//           is not finite is a breakdown.
+template <typename V, int T, int MODE>
+__global__ __launch_bounds__(kBS) void k_rz(long cap, const V* __restrict__ r, const V* __restrict__ z,
+                                            ColState* cs, GridRed red) {
+  using VT = typename Vec16<V>::type;
+  constexpr int N = Vec16<V>::N;
+  __shared__ double sh[kBS * N];
+  __shared__ double vals[kMaxTile];
+  if (MODE == 1 && cs->n_active == 0) return;
+  const int t = threadIdx.x;
+  double acc[1][N];
+#pragma unroll
+  for (int v = 0; v < N; ++v) acc[0][v] = 0.0;
+  const long nv = cap / N;
+  for (long i = (long)blockIdx.x * kBS + t; i < nv; i += (long)gridDim.x * kBS) {
+    const VT rv = reinterpret_cast<const VT*>(r)[i];
+    const VT zv = reinterpret_cast<const VT*>(z)[i];
+    const V* rs = reinterpret_cast<const V*>(&rv);
+    const V* zs = reinterpret_cast<const V*>(&zv);
+#pragma unroll
+    for (int v = 0; v < N; ++v) acc[0][v] += (double)rs[v] * (double)zs[v];
+  }
+  block_reduce_cols<kBS, 1, N>(acc, T, sh);
+  if (t < T) vals[t] = sh[t];
+  __syncthreads();
+  if (!grid_reduce<kBS>(vals, T, red)) return;
+  if (t < T) {
+    const double rz = vals[t];
+    if constexpr (MODE == 0) {
+      cs->rho[t] = rz;
+      if (cs->active[t] && !(rz > 0.0)) cs->active[t] = 0;
+    } else {
+      double be = 0.0;
+      if (cs->active[t]) {
+        if (!isfinite(rz)) {
+          cs->active[t] = 0;
+          cs->status[t] = kStBreak;
+          cs->oactive[t] = 0;
+        } else if (!(rz > 0.0)) {
+          cs->active[t] = 0;
+        } else {
+          be = rz / cs->rho[t];
+          cs->rho[t] = rz;
+        }
+      }
+      cs->beta[t] = be;
+    }
+  }
+  recount_active(cs, T);
+}
+
+// p = z + beta p (z = L_T^+ r)
+template <typename V, int T>
+__global__ __launch_bounds__(kBS) void k_direction_z(long cap, V* __restrict__ p,
+                                                     const V* __restrict__ z, const ColState* cs) {
+  using VT = typename Vec16<V>::type;
+  constexpr int N = Vec16<V>::N;
+  if (cs->n_active == 0) return;
+  const int t = threadIdx.x;
+  V be[N];
+#pragma unroll
+  for (int v = 0; v < N; ++v) be[v] = (V)cs->beta[(t * N + v) % T];
+  const long nv = cap / N;
+  for (long i = (long)blockIdx.x * kBS + t; i < nv; i += (long)gridDim.x * kBS) {
+    VT pv = reinterpret_cast<const VT*>(p)[i];
+    const VT zv = reinterpret_cast<const VT*>(z)[i];
+    V* ps = reinterpret_cast<V*>(&pv);
+    const V* zs = reinterpret_cast<const V*>(&zv);
+#pragma unroll
+    for (int v = 0; v < N; ++v) ps[v] = zs[v] + be[v] * ps[v];
     reinterpret_cast<VT*>(p)[i] = pv;
   }
 }
@@ -566,6 +653,17 @@ static nvd_status poll(Workspace* ws, hipStream_t s, int* n_active, int* n_oacti
 }
 
 // CG iterations until no column of the tile is active.
+// Start of a tree-preconditioned CG run on r: p = z = L_T^+ r, rho = r^T z.
+template <typename V>
+static nvd_status tree_start(DevGraph* g, Workspace* ws, int T, const V* r, V* p, hipStream_t s) {
+  const long cap = (long)padded_cap(g->n, T);
+  const int sgrid = stream_grid(cap / Vec16<V>::N);
+  NVD_TRY(tree_solve(g, sizeof(V) == 8 ? 0 : 1, T, r, p, s));
+  NVD_TILE_SWITCH(T, (k_rz<V, TT, 0><<<sgrid, kBS, 0, s>>>(cap, r, p, ws->cs, ws->red)));
+  NVD_HIP(hipGetLastError());
+  return NVD_OK;
+}
+
 template <typename V>
 static nvd_status cg_loop(DevGraph* g, Workspace* ws, int T, V* x, V* r, V* p, V* q,
                           const V* invd, double rtol2, int max_iter, const SolveParams& sp,
@@ -604,12 +702,24 @@ static nvd_status cg_loop(DevGraph* g, Workspace* ws, int T, V* x, V* r, V* p, V
       NVD_TRY(launch_spmm(sc, ws->red, s));
       ids.push_back(prof_last_id());
       int pid = prof_begin(s, sizeof(V) == 8 ? PK_UPD64 : PK_UPD32, upd_bytes);
-      NVD_TILE_SWITCH(T, (k_update<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, x, r, p, q, invd, rtol2,
-                                                                max_iter, ws->cs, ws->red)));
+      if (sp.tree) {
+        NVD_TILE_SWITCH(T, (k_update<V, TT, true><<<sgrid, kBS, 0, s>>>(
+                               g->n, cap, x, r, p, q, invd, rtol2, max_iter, ws->cs, ws->red)));
+      } else {
+        NVD_TILE_SWITCH(T, (k_update<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, x, r, p, q, invd, rtol2,
+                                                                  max_iter, ws->cs, ws->red)));
+      }
       prof_end(s, pid);
       ids.push_back(pid);
       pid = prof_begin(s, sizeof(V) == 8 ? PK_DIR64 : PK_DIR32, dir_bytes);
-      NVD_TILE_SWITCH(T, (k_direction<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, p, r, invd, ws->cs)));
+      if (sp.tree) {
+        // z = L_T^+ r into q (free until the next apply), then beta and p
+        NVD_TRY(tree_solve(g, sizeof(V) == 8 ? 0 : 1, T, r, q, s));
+        NVD_TILE_SWITCH(T, (k_rz<V, TT, 1><<<sgrid, kBS, 0, s>>>(cap, r, q, ws->cs, ws->red)));
+        NVD_TILE_SWITCH(T, (k_direction_z<V, TT><<<sgrid, kBS, 0, s>>>(cap, p, q, ws->cs)));
+      } else {
+        NVD_TILE_SWITCH(T, (k_direction<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, p, r, invd, ws->cs)));
+      }
       prof_end(s, pid);
       ids.push_back(pid);
     }
@@ -784,6 +894,7 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
                       nvd_pair_info* info_dev, hipStream_t s) {
   const bool mixed = sp.precision == NVD_MIXED;
   NVD_TRY(ensure_workspace(g, T, mixed));
+  if (sp.tree) NVD_TRY(ensure_tree(g, T));
   Workspace* ws = g->ws;
   const int n = g->n;
   const long cap = (long)padded_cap(n, T);
@@ -797,6 +908,7 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
                          n, cap, ProjSrc{P, ld, Q, ld}, m, g->invd64, ws->b64, ws->x64, ws->r64,
                          ws->p64, ws->q64, mixed ? 0 : 1, ws->cs, ws->red)));
   NVD_HIP(hipGetLastError());
+  if (sp.tree && !mixed) NVD_TRY(tree_start<double>(g, ws, T, ws->r64, ws->p64, s));
 
   SpmmCall resid{};
   resid.g = g;
@@ -828,6 +940,7 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
       NVD_TILE_SWITCH(T, (k_restart<TT><<<grid, kBS, 0, s>>>(n, cap, ws->r64, ws->p64, ws->q64,
                                                              g->invd64, ws->cs, ws->red)));
       NVD_HIP(hipGetLastError());
+      if (sp.tree) NVD_TRY(tree_start<double>(g, ws, T, ws->r64, ws->p64, s));
     }
     int restarts = 0;
     for (;;) {
@@ -847,6 +960,7 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
       NVD_TILE_SWITCH(T, (k_restart<TT><<<grid, kBS, 0, s>>>(n, cap, ws->r64, ws->p64, ws->q64,
                                                              g->invd64, ws->cs, ws->red)));
       NVD_HIP(hipGetLastError());
+      if (sp.tree) NVD_TRY(tree_start<double>(g, ws, T, ws->r64, ws->p64, s));
     }
   } else {
     const double irtol2 = sp.inner_rtol * sp.inner_rtol;
@@ -877,6 +991,7 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
                                             ws->p32, ws->q32, rtol2, irtol2, sp.max_refine,
                                             first ? 1 : 0, ws->cs, ws->red);
       NVD_HIP(hipGetLastError());
+      if (sp.tree) NVD_TRY(tree_start<float>(g, ws, T, ws->r32, ws->p32, s));
       if (first || !connected) {
         int no = 0;
         NVD_TRY(poll(ws, s, nullptr, &no));

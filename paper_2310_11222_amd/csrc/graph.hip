@@ -520,6 +520,7 @@ nvd_status graph_destroy(DevGraph* g) {
   if (!g) return NVD_OK;
   (void)hipDeviceSynchronize();
   if (g->ws) free_workspace(g->ws);
+  free_tree(g->tree);
   free_graph_arrays(g);
   delete g;
   return NVD_OK;

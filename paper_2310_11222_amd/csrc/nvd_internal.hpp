@@ -85,6 +85,21 @@ struct LongRows {
 // ---------------------------------------------------------------------------
 struct Workspace;
 
+// Spanning forest for the tree preconditioner (built on first use): Euler
+// tour positions, inverse edge weights to the parent, and scan buffers.
+struct TreePre {
+  int* tin = nullptr;          // [n] tour position where v is entered (0 .. 2n-1)
+  int* tout = nullptr;         // [n] tour position where v is left
+  double* winv = nullptr;      // [n] 1 / weight of the edge to the parent (0 at roots)
+  int* rbeg = nullptr;         // [n] tin of v's root: v's component is the tour
+  int* rend = nullptr;         // [n] range [rbeg, rend] (tout of the root)
+  double* E = nullptr;         // [2n][cap_tile] tour values
+  double* S = nullptr;         // [2n][cap_tile] their prefix sums
+  double* part = nullptr;      // [chunks][cap_tile] scan offsets
+  int cap_tile = 0;
+  int n_tree_edges = 0;
+};
+
 struct DevGraph {
   int n = 0;
   int nnz = 0;                 // internal nnz (self-loops removed)
@@ -117,6 +132,7 @@ struct DevGraph {
   Workspace* ws = nullptr;
   int tuned_tile[2][8] = {};   // [precision][log2 k bucket] -> tile (0 = not tuned)
   int tuned_nl[2][8] = {};     // [precision][log2 tile] -> neighbour lanes (0 = default)
+  TreePre* tree = nullptr;     // spanning forest, built when first needed
 };
 
 struct Workspace {
@@ -190,12 +206,18 @@ struct SolveParams {
   int nl;                   // SpMM lanes per row across neighbours (0 = default)
   int grid;                 // SpMM short-row grid (0 = default)
   bool warm;
+  bool tree;                // spanning-tree preconditioner instead of Jacobi
 };
 nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
                       const SolveParams& sp, double* d_out, double* X, int64_t ldx,
                       nvd_pair_info* info_dev, hipStream_t s);
 nvd_status project_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
                         double* Dbar, int64_t ldd, double* norms, hipStream_t s);
+// Tree preconditioner (tree.hip): set up for tiles up to T; z = L_T^+ r.
+nvd_status ensure_tree(DevGraph* g, int T);
+nvd_status tree_solve(DevGraph* g, int prec, int T, const void* r, void* z, hipStream_t s);
+void free_tree(TreePre* tp);
+
 // Validation of solver options (NVD_E_ARG with a message).
 nvd_status check_solve_opts(const nvd_opts* o);
 int choose_tile(DevGraph* g, int k, int precision, hipStream_t s);

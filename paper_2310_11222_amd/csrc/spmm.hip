@@ -2,6 +2,15 @@
 // paper's section 3.1), for a tile of T right-hand-side columns stored
 // row-major, in FP64 or FP32.
 //
+// Each row is accumulated as a sum of edge differences,
+//   (L x)_v = sum_u w_vu (x_v - x_u),
+// not as d_v x_v - sum_u w_vu x_u: the rounding error is then relative to
+// the differences across edges rather than to |x|.  The two differ little
+// for rough x, but a smooth x with a large spread (what a strong
+// preconditioner such as a spanning tree produces on long paths, and any
+// solution on an ill-conditioned graph) loses most of its FP32 digits in the
+// second form.  The degree is not read at all.
+//
 // Work split:
 //  * short rows (<= kLongRow neighbours): a group of G = L*NL lanes per row,
 //    where L = T/VW lanes cover one row of X with 16-byte vectors (VW
@@ -40,7 +49,6 @@ struct SpmmK {
   const int* rp;
   const int* ci;
   const V* w;      // null for unit weights
-  const V* deg;    // null for unit weights
   const V* x;
   long ldx;
   V* y;
@@ -70,14 +78,14 @@ constexpr int kSpmmR = NVD_SPMM_R;
 // blocks than this lengthen the grid reduction's tail.
 constexpr int kSpmmMaxShortGrid = kMaxBlocks - 1024;
 
-// Epilogue for VW columns c0 .. c0+VW-1 of one row; sum = (A x) entries.
+// Epilogue for VW columns c0 .. c0+VW-1 of one row; sum = (L x) entries.
 template <typename V, int VW, bool UNIT, int EPI, int NDA>
 __device__ __forceinline__ void spmm_epilogue(const SpmmK<V>& a, int row, int cv, const V (&sum)[VW],
-                                              const V (&own)[VW], V dg, double (&acc)[NDA][VW]) {
+                                              const V (&own)[VW], double (&acc)[NDA][VW]) {
   using VV = typename VecOf<V, VW>::type;
   V yv[VW];
 #pragma unroll
-  for (int v = 0; v < VW; ++v) yv[v] = dg * own[v] - sum[v];
+  for (int v = 0; v < VW; ++v) yv[v] = sum[v];
   VV* yp = reinterpret_cast<VV*>(a.y + (long)row * a.ldy) + cv;
   if constexpr (EPI == EPI_PLAIN) {
     __builtin_nontemporal_store(pack<V, VW>(yv), yp);
@@ -102,14 +110,6 @@ __device__ __forceinline__ void spmm_epilogue(const SpmmK<V>& a, int row, int cv
     }
     __builtin_nontemporal_store(pack<V, VW>(rv), yp);
   }
-}
-
-template <typename V, int VW, bool UNIT>
-__device__ __forceinline__ V row_degree(const SpmmK<V>& a, int row) {
-  if constexpr (UNIT)
-    return (V)(a.rp[row + 1] - a.rp[row]);
-  else
-    return a.deg[row];
 }
 
 template <typename V, int T, int NL, bool UNIT, int EPI, bool VEC>
@@ -149,7 +149,8 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
       const int row = lr.seg_row[s];
       const int lo = lr.seg_lo[s];
       const int hi = lr.seg_hi[s];
-      V sum[VW];
+      V sum[VW], xr[VW];
+      unpack<V, VW>(X[(long)row * ldxv + cv], xr);
 #pragma unroll
       for (int v = 0; v < VW; ++v) sum[v] = (V)0;
       for (int e = lo + j; e < hi; e += NJ) {
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
         V xv[VW];
         unpack<V, VW>(X[(long)col * ldxv + cv], xv);
 #pragma unroll
-        for (int v = 0; v < VW; ++v) sum[v] += wt * xv[v];
+        for (int v = 0; v < VW; ++v) sum[v] += wt * (xr[v] - xv[v]);
       }
       double part[1][VW];
 #pragma unroll
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
 #pragma unroll
           for (int v = 0; v < VW; ++v) tot[v] = (V)sh_long[t * VW + v];
           unpack<V, VW>(X[(long)row * ldxv + t], own);
-          spmm_epilogue<V, VW, UNIT, EPI, NDA>(a, row, t, tot, own, row_degree<V, VW, UNIT>(a, row), acc);
+          spmm_epilogue<V, VW, UNIT, EPI, NDA>(a, row, t, tot, own, acc);
         }
       } else {
         if (t < T) st_agent(&lr.seg_part[(long)s * kMaxTile + t], sh_long[t]);
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
               tot[v] = (V)sacc;
             }
             unpack<V, VW>(X[(long)row * ldxv + t], own);
-            spmm_epilogue<V, VW, UNIT, EPI, NDA>(a, row, t, tot, own, row_degree<V, VW, UNIT>(a, row), acc);
+            spmm_epilogue<V, VW, UNIT, EPI, NDA>(a, row, t, tot, own, acc);
           }
           if (t == 0) lr.row_tick[first] = 0u;
         }
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
     for (int base = sb * ROWS_PER_STEP; base < a.n; base += nsb * ROWS_PER_STEP) {
       int row[R], rs[R], deg[R];
       bool mine[R];
-      V own[R][VW], dg[R];
+      V own[R][VW];
       int mx = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -243,10 +244,6 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
       for (int r = 0; r < R; ++r) {
         const int orow = mine[r] ? row[r] : 0;
         unpack<V, VW>(X[(long)orow * ldxv + cv], own[r]);
-        if constexpr (UNIT)
-          dg[r] = (V)deg[r];
-        else
-          dg[r] = mine[r] ? a.deg[row[r]] : (V)0;
       }
       V sum[R][VW];
 #pragma unroll
@@ -288,7 +285,7 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
             V xs[VW];
             unpack<V, VW>(xv[r][u], xs);
 #pragma unroll
-            for (int v = 0; v < VW; ++v) sum[r][v] += wt[r][u] * xs[v];
+            for (int v = 0; v < VW; ++v) sum[r][v] += wt[r][u] * (own[r][v] - xs[v]);
           }
       }
 #pragma unroll
@@ -300,7 +297,7 @@ __global__ __launch_bounds__(kBS) void k_spmm(SpmmK<V> a, GridRed red, LongRows 
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (j == 0 && mine[r])
-          spmm_epilogue<V, VW, UNIT, EPI, NDA>(a, row[r], cv, sum[r], own[r], dg[r], acc);
+          spmm_epilogue<V, VW, UNIT, EPI, NDA>(a, row[r], cv, sum[r], own[r], acc);
       }
     }
   }
@@ -441,13 +438,10 @@ static nvd_status launch_typed(const SpmmCall& c, const GridRed& red, hipStream_
   k.rp = g->rp;
   k.ci = g->ci;
   const bool unit = !g->weighted;
-  if constexpr (sizeof(V) == 8) {
+  if constexpr (sizeof(V) == 8)
     k.w = g->w64;
-    k.deg = g->deg64;
-  } else {
+  else
     k.w = g->w32;
-    k.deg = g->deg32;
-  }
   k.x = static_cast<const V*>(c.x);
   k.ldx = c.ldx;
   k.y = static_cast<V*>(c.y);
@@ -478,7 +472,7 @@ static nvd_status launch_typed(const SpmmCall& c, const GridRed& red, hipStream_
     const double sv = (double)sizeof(V);
     const double sw = unit ? 0.0 : sv;
     const double n = g->n;
-    const double csr = (4.0 + sw) * g->nnz + 4.0 * (n + 1) + sw * n;
+    const double csr = (4.0 + sw) * g->nnz + 4.0 * (n + 1);
     const double vecb = c.epi == EPI_RESID ? 3.0 * c.T * 8.0 * n : 2.0 * c.T * sv * n;
     pid = prof_begin(s, sizeof(V) == 8 ? PK_SPMM64 : PK_SPMM32, csr + vecb);
   }

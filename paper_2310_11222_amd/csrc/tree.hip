@@ -1,0 +1,326 @@
+// Spanning-tree preconditioner: z = L_T^+ r for a spanning forest T of the
+// graph (the tree-based preconditioners of section 3.2; here a plain
+// breadth-first spanning forest, without the augmentation of the paper's
+// "Aug Tree" solver).
+//
+// On a tree, L_T x = r has a closed solution (the flow formula): the flow on
+// the edge from v to its parent is the sum f_v of r over v's subtree, the
+// potential drops by f_v / w_v across that edge, and the root is held at 0.
+// Both sums are prefix sums over an Euler tour of the forest (every node
+// entered at tin[v] and left at tout[v], 2n events; a component is the
+// contiguous tour range of its root, each node counted twice):
+//   f_v = S1[tout_v] - S1[tin_v] + r_v - mu_c size_v,
+//         S1 = prefix of (r_v at tin_v, 0 at tout_v), mu_c = mean of r over
+//         v's component c, size_v = (tout_v - tin_v + 1) / 2
+//   x_v = S2[tin_v],  S2 = prefix of (+f_v/w_v at tin_v, -f_v/w_v at tout_v)
+// so one solve is two scans over 2n x T values, O(n) work in O(log n)
+// depth whatever the depth of the tree.  The scans run in FP64 (prefix sums
+// cancel) with a fixed chunk and segment split, so results repeat bit for
+// bit.
+//
+// Subtracting mu_c makes the map the pseudoinverse on r's component means
+// too (constants go to zero).  Without it the solve would be the grounded
+// inverse, whose image of a constant grows like n times the tree depth: the
+// small mean that rounding leaves in the solver's residual (FP32 above all)
+// would swamp z.  Roots get potential 0, so z is L_T^+ r plus a constant
+// per component, which does not change r^T z for r orthogonal to the
+// constants and which the solver's projections remove.
+#include <algorithm>
+#include <vector>
+
+#include "device_common.hpp"
+
+namespace nvd {
+
+constexpr int kScanChunk = 2048;   // tour rows per scan block
+
+// ---------------------------------------------------------------------------
+// host: spanning forest and Euler tour
+// ---------------------------------------------------------------------------
+static nvd_status build_tree(DevGraph* g) {
+  const int n = g->n;
+  const std::vector<int>& rp = g->h_rp;
+  const std::vector<int>& ci = g->h_ci;
+  const bool weighted = !g->h_w.empty();
+  std::vector<int> parent(n, -1);
+  std::vector<double> pw(n, 0.0);
+  std::vector<char> seen(n, 0);
+  std::vector<int> queue;
+  queue.reserve(n);
+  int tree_edges = 0;
+  for (int s = 0; s < n; ++s) {          // a root per component: its smallest node
+    if (seen[s]) continue;
+    seen[s] = 1;
+    size_t head = queue.size();
+    queue.push_back(s);
+    for (; head < queue.size(); ++head) {
+      const int v = queue[head];
+      for (int e = rp[v]; e < rp[v + 1]; ++e) {
+        const int u = ci[e];
+        if (seen[u]) continue;
+        seen[u] = 1;
+        parent[u] = v;
+        pw[u] = weighted ? g->h_w[e] : 1.0;
+        queue.push_back(u);
+        ++tree_edges;
+      }
+    }
+  }
+  // children lists (CSR), then an iterative depth-first Euler tour
+  std::vector<int> coff(n + 1, 0), kids(std::max(tree_edges, 1));
+  for (int v = 0; v < n; ++v)
+    if (parent[v] >= 0) ++coff[parent[v] + 1];
+  for (int v = 0; v < n; ++v) coff[v + 1] += coff[v];
+  {
+    std::vector<int> fill(coff.begin(), coff.end() - 1);
+    for (int v = 0; v < n; ++v)
+      if (parent[v] >= 0) kids[fill[parent[v]]++] = v;
+  }
+  std::vector<int> tin(n), tout(n), root_of(n);
+  std::vector<std::pair<int, int>> stack;
+  int t = 0;
+  for (int root = 0; root < n; ++root) {
+    if (parent[root] >= 0) continue;
+    root_of[root] = root;
+    tin[root] = t++;
+    stack.emplace_back(root, coff[root]);
+    while (!stack.empty()) {
+      auto& top = stack.back();
+      const int v = top.first;
+      if (top.second < coff[v + 1]) {
+        const int c = kids[top.second++];
+        root_of[c] = root_of[v];
+        tin[c] = t++;
+        stack.emplace_back(c, coff[c]);
+      } else {
+        tout[v] = t++;
+        stack.pop_back();
+      }
+    }
+  }
+  std::vector<double> winv(n);
+  std::vector<int> rbeg(n), rend(n);
+  for (int v = 0; v < n; ++v) {
+    winv[v] = parent[v] >= 0 ? 1.0 / pw[v] : 0.0;
+    rbeg[v] = tin[root_of[v]];
+    rend[v] = tout[root_of[v]];
+  }
+  TreePre* tp = new TreePre();
+  tp->n_tree_edges = tree_edges;
+  nvd_status st = NVD_OK;
+  auto al = [&](void** p, size_t bytes) {
+    if (st == NVD_OK && hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
+      set_error("tree preconditioner: out of device memory");
+      st = NVD_E_NOMEM;
+    }
+  };
+  al((void**)&tp->tin, sizeof(int) * n);
+  al((void**)&tp->tout, sizeof(int) * n);
+  al((void**)&tp->winv, sizeof(double) * n);
+  al((void**)&tp->rbeg, sizeof(int) * n);
+  al((void**)&tp->rend, sizeof(int) * n);
+  if (st == NVD_OK &&
+      (hipMemcpy(tp->tin, tin.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(tp->tout, tout.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(tp->rbeg, rbeg.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(tp->rend, rend.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(tp->winv, winv.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess)) {
+    set_error("tree preconditioner: upload failed");
+    st = NVD_E_DEVICE;
+  }
+  if (st != NVD_OK) {
+    free_tree(tp);
+    return st;
+  }
+  g->tree = tp;
+  return NVD_OK;
+}
+
+void free_tree(TreePre* tp) {
+  if (!tp) return;
+  void* ptrs[] = {tp->tin, tp->tout, tp->winv, tp->rbeg, tp->rend, tp->E, tp->S, tp->part};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete tp;
+}
+
+nvd_status ensure_tree(DevGraph* g, int T) {
+  if (!g->tree) NVD_TRY(build_tree(g));
+  TreePre* tp = g->tree;
+  if (tp->cap_tile >= T) return NVD_OK;
+  void* ptrs[] = {tp->E, tp->S, tp->part};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  tp->E = tp->S = tp->part = nullptr;
+  const size_t rows = 2 * (size_t)g->n;
+  const size_t nchunk = (rows + kScanChunk - 1) / kScanChunk;
+  NVD_HIP(hipMalloc((void**)&tp->E, sizeof(double) * rows * T));
+  NVD_HIP(hipMalloc((void**)&tp->S, sizeof(double) * rows * T));
+  NVD_HIP(hipMalloc((void**)&tp->part, sizeof(double) * nchunk * T));
+  tp->cap_tile = T;
+  return NVD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+// E[tin_v] = r_v, E[tout_v] = 0
+template <typename V>
+__global__ void k_tour_put(int n, int T, const V* __restrict__ r, const int* __restrict__ tin,
+                           const int* __restrict__ tout, double* __restrict__ E) {
+  const long tot = (long)n * T;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+    const long v = e / T;
+    const int c = (int)(e % T);
+    E[(long)tin[v] * T + c] = (double)r[e];
+    E[(long)tout[v] * T + c] = 0.0;
+  }
+}
+
+// f_v = S[tout_v] - S[tin_v] + r_v - mu size_v; y = f_v / w_v;
+// E[tin_v] = y, E[tout_v] = -y
+template <typename V>
+__global__ void k_tour_flow(int n, int T, const V* __restrict__ r, const int* __restrict__ tin,
+                            const int* __restrict__ tout, const int* __restrict__ rbeg,
+                            const int* __restrict__ rend, const double* __restrict__ winv,
+                            const double* __restrict__ S, double* __restrict__ E) {
+  const long tot = (long)n * T;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+    const long v = e / T;
+    const int c = (int)(e % T);
+    const int ti = tin[v], to = tout[v], rb = rbeg[v], re = rend[v];
+    const long a = (long)ti * T + c, b = (long)to * T + c;
+    // component sum: the inclusive prefix over the root's tour range
+    const double csum = S[(long)re * T + c] - (rb > 0 ? S[(long)(rb - 1) * T + c] : 0.0);
+    const double mu = csum / (double)((re - rb + 1) / 2);
+    const double f = S[b] - S[a] + (double)r[e] - mu * (double)((to - ti + 1) / 2);
+    const double y = f * winv[v];
+    E[a] = y;
+    E[b] = -y;
+  }
+}
+
+// z_v = S[tin_v]
+template <typename V>
+__global__ void k_tour_get(int n, int T, const double* __restrict__ S, const int* __restrict__ tin,
+                           V* __restrict__ z) {
+  const long tot = (long)n * T;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x)
+    z[e] = (V)S[(long)tin[e / T] * T + e % T];
+}
+
+// Scan of a rows x T row-major array along the rows, per column.  Block b
+// owns rows [b*chunk, (b+1)*chunk); inside it lane j of a column (NJ = 256/T
+// lanes) owns a contiguous segment.  Phase 1: chunk sums; phase 2: exclusive
+// scan of the chunk sums per column; phase 3: segment prefixes plus the
+// chunk offset.  The split is the same in phases 1 and 3.
+__device__ __forceinline__ void seg_of(int T, long rows, int b, long* lo, long* hi, int* c) {
+  const int t = threadIdx.x;
+  const int NJ = 256 / T;
+  const int j = t / T;
+  *c = t % T;
+  const long seg = (kScanChunk + NJ - 1) / NJ;
+  const long base = (long)b * kScanChunk;
+  const long end = min(rows, base + kScanChunk);
+  *lo = min(end, base + j * seg);
+  *hi = min(end, *lo + seg);
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(long rows, int T, const double* __restrict__ E,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[256];
+  long lo, hi;
+  int c;
+  seg_of(T, rows, blockIdx.x, &lo, &hi, &c);
+  double s = 0.0;
+  for (long i = lo; i < hi; ++i) s += E[i * T + c];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if ((int)threadIdx.x < T) {
+    double tot = 0.0;
+    for (int j = 0; j < 256 / T; ++j) tot += sh[j * T + threadIdx.x];
+    part[(long)blockIdx.x * T + threadIdx.x] = tot;
+  }
+}
+
+// one block per column: exclusive scan of part[b][c] over b, in place
+__global__ __launch_bounds__(256) void k_scan_offsets(int nchunk, int T, double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int c = blockIdx.x;
+  const int t = threadIdx.x;
+  const int per = (nchunk + 255) / 256;
+  const int b0 = min(nchunk, t * per), b1 = min(nchunk, b0 + per);
+  double s = 0.0;
+  for (int b = b0; b < b1; ++b) s += part[(long)b * T + c];
+  sh[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    double run = 0.0;
+    for (int i = 0; i < 256; ++i) {
+      const double v = sh[i];
+      sh[i] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  double run = sh[t];
+  for (int b = b0; b < b1; ++b) {
+    const double v = part[(long)b * T + c];
+    part[(long)b * T + c] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(long rows, int T, const double* __restrict__ E,
+                                                    const double* __restrict__ part,
+                                                    double* __restrict__ S) {
+  __shared__ double sh[256];
+  long lo, hi;
+  int c;
+  seg_of(T, rows, blockIdx.x, &lo, &hi, &c);
+  double s = 0.0;
+  for (long i = lo; i < hi; ++i) s += E[i * T + c];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  const int j = threadIdx.x / T;
+  double run = part[(long)blockIdx.x * T + c];
+  for (int q = 0; q < j; ++q) run += sh[q * T + c];
+  for (long i = lo; i < hi; ++i) {
+    run += E[i * T + c];
+    S[i * T + c] = run;
+  }
+}
+
+static void scan_rows(long rows, int T, const double* E, double* part, double* S, hipStream_t s) {
+  const int nchunk = (int)((rows + kScanChunk - 1) / kScanChunk);
+  k_scan_sums<<<nchunk, 256, 0, s>>>(rows, T, E, part);
+  k_scan_offsets<<<T, 256, 0, s>>>(nchunk, T, part);
+  k_scan_apply<<<nchunk, 256, 0, s>>>(rows, T, E, part, S);
+}
+
+template <typename V>
+static nvd_status tree_solve_t(DevGraph* g, int T, const V* r, V* z, hipStream_t s) {
+  TreePre* tp = g->tree;
+  const int n = g->n;
+  const long rows = 2L * n;
+  const int grid = (int)std::min<long>(4096, ((long)n * T + 255) / 256);
+  k_tour_put<V><<<std::max(grid, 1), 256, 0, s>>>(n, T, r, tp->tin, tp->tout, tp->E);
+  scan_rows(rows, T, tp->E, tp->part, tp->S, s);
+  k_tour_flow<V><<<std::max(grid, 1), 256, 0, s>>>(n, T, r, tp->tin, tp->tout, tp->rbeg, tp->rend,
+                                                   tp->winv, tp->S, tp->E);
+  scan_rows(rows, T, tp->E, tp->part, tp->S, s);
+  k_tour_get<V><<<std::max(grid, 1), 256, 0, s>>>(n, T, tp->S, tp->tin, z);
+  NVD_HIP(hipGetLastError());
+  return NVD_OK;
+}
+
+nvd_status tree_solve(DevGraph* g, int prec, int T, const void* r, void* z, hipStream_t s) {
+  if (!g->tree || g->tree->cap_tile < T) {
+    set_error("tree preconditioner: not set up for this tile");
+    return NVD_E_DEVICE;
+  }
+  return prec == 0 ? tree_solve_t<double>(g, T, static_cast<const double*>(r), static_cast<double*>(z), s)
+                   : tree_solve_t<float>(g, T, static_cast<const float*>(r), static_cast<float*>(z), s);
+}
+
+}  // namespace nvd

@@ -1,0 +1,132 @@
+"""GPU parity of the spanning-tree preconditioner (NVD_PRECOND_TREE):
+exact on trees (one CG iteration), a rank-one correction on cycles, and far
+fewer iterations than the Jacobi diagonal on the tree-like graphs of the
+density sweep (on a graph with many edges off a breadth-first tree the
+Jacobi diagonal is the better of the two; there only parity is checked);
+distances against the oracle's exact routes everywhere."""
+import numpy as np
+import pytest
+
+import oracle
+from nvdgen import (random_tree, cycle_graph, barabasi_albert, density_graph, Graph,
+                    sparse_support_pairs)
+
+from gpu_helpers import say, dev_graph, rel_err
+
+pytestmark = pytest.mark.gpu
+
+PREC = [("fp64", 1e-10, 1e-8), ("mixed", 1e-8, 1e-6)]
+
+
+@pytest.mark.parametrize("precision,rtol,tol", PREC)
+def test_tree_graph_is_solved_exactly(precision, rtol, tol):
+    rng = np.random.default_rng(1)
+    n = 100_000
+    t = random_tree(n, rng, rng.uniform(0.2, 5.0, n - 1))
+    P, Q = sparse_support_pairs(n, 16, 0.05, rng)
+    say("tree exact", precision)
+    dg = dev_graph(t)
+    d, _, info = dg.distances(P, Q, precision=precision, rtol=rtol, precond="tree")
+    ref = oracle.ge_tree(t.n, t.row_ptr, t.col_idx, t.w, P, Q)["d"]
+    assert rel_err(d.cpu().numpy(), ref).max() <= tol
+    assert all(i["status"] == 0 for i in info)
+    # the preconditioner is the inverse: one iteration per (inner) solve
+    assert max(i["iters"] for i in info) <= (2 if precision == "fp64" else 6), info[0]
+
+
+@pytest.mark.parametrize("n,precision,rtol,tol,max_its", [
+    (20_000, "fp64", 1e-10, 1e-8, 8),
+    (20_000, "mixed", 1e-8, 1e-6, 40),
+    # a path of depth 1e5 in the tree: x spans ~1e6 times its local scale,
+    # so the FP64 residual floor (rounding of x under L) is near 1e-9
+    (200_000, "fp64", 1e-8, 1e-8, 8),
+    (200_000, "mixed", 1e-8, 1e-6, 40),
+])
+def test_cycle_rank_one_off_tree(n, precision, rtol, tol, max_its):
+    """A cycle is its breadth-first tree plus one edge: the preconditioned
+    operator is the identity plus a rank-one term, two CG iterations in
+    exact arithmetic (a few more with rounding and restarts)."""
+    g = cycle_graph(n)
+    rng = np.random.default_rng(2)
+    P, Q = sparse_support_pairs(n, 8, 0.01, rng)
+    say("tree cycle", n, precision)
+    dg = dev_graph(g)
+    d, _, info = dg.distances(P, Q, precision=precision, rtol=rtol, precond="tree")
+    ref = oracle.ge_cycle(n, P, Q)["d"]
+    assert rel_err(d.cpu().numpy(), ref).max() <= tol
+    assert all(i["status"] == 0 for i in info), [(i["status"], i["rel_res"]) for i in info]
+    assert max(i["iters"] for i in info) <= max_its, info[0]
+
+
+@pytest.mark.parametrize("model,deg,tree_like", [("ws", 1, True), ("ws", 2, True), ("ba", 1, True),
+                                                  ("er", 1, True), ("sbm", 2, False)])
+def test_sparse_density_graphs_fewer_iterations(model, deg, tree_like):
+    g, P, Q = density_graph(model, deg)
+    ref = oracle.ge_grounded(g.n, g.row_ptr, g.col_idx, None, P, Q, sparse=True)["d"]
+    say("tree density", model, deg)
+    dg = dev_graph(g)
+    its = {}
+    for pre in ("jacobi", "tree"):
+        for precision, rtol, tol in PREC:
+            d, _, info = dg.distances(P, Q, precision=precision, rtol=rtol, precond=pre)
+            assert rel_err(d.cpu().numpy(), ref).max() <= tol, (pre, precision)
+            assert all(i["status"] == 0 for i in info)
+            its[(pre, precision)] = max(i["iters"] for i in info)
+    say("iterations", its)
+    if tree_like:
+        assert its[("tree", "fp64")] * 5 <= its[("jacobi", "fp64")], its
+        assert its[("tree", "mixed")] * 5 <= its[("jacobi", "mixed")], its
+
+
+@pytest.mark.parametrize("precision,rtol,tol", PREC)
+def test_general_weighted_disconnected_graph(precision, rtol, tol):
+    """Not a tree: a weighted BA graph plus a separate cycle and isolated
+    nodes (four components), a hub with a split row; dense oracle."""
+    rng = np.random.default_rng(3)
+    b = barabasi_albert(1500, 3, rng)
+    nc = 40
+    cu = np.arange(nc) + b.n
+    cv = (np.arange(nc) + 1) % nc + b.n
+    hub_nb = rng.choice(b.n, 600, replace=False)
+    n = b.n + nc + 3
+    eu = np.concatenate([b.eu, np.minimum(cu, cv), hub_nb])
+    ev = np.concatenate([b.ev, np.maximum(cu, cv), np.full(600, n - 1)])
+    g = Graph(n, eu, ev)
+    g = g.with_weights(rng.lognormal(0, 1, g.num_edges))
+    P = rng.random((n, 5))
+    Q = rng.random((n, 5))
+    say("tree general", precision)
+    dg = dev_graph(g)
+    assert dg.stats()["n_comp"] == 4
+    d, _, info = dg.distances(P, Q, precision=precision, rtol=rtol, precond="tree")
+    ref = oracle.ge_dense(g.n, g.row_ptr, g.col_idx, g.w, P, Q)["d"]
+    assert rel_err(d.cpu().numpy(), ref).max() <= tol
+    assert all(i["status"] == 0 for i in info)
+
+
+def test_pairwise_with_tree_preconditioner():
+    g, P, _ = density_graph("ws", 2)
+    V = P[:, :6]
+    say("tree pairwise")
+    dg = dev_graph(g)
+    D, _, info = dg.pairwise(V, precision="fp64", rtol=1e-10, precond="tree")
+    iu, ju = np.triu_indices(6, 1)
+    ref = oracle.ge_grounded(g.n, g.row_ptr, g.col_idx, None, V[:, iu], V[:, ju], sparse=True)["d"]
+    assert rel_err(D.cpu().numpy()[iu, ju], ref).max() <= 1e-8
+
+
+def test_batches_reject_tree_flag():
+    import paper_2310_11222_amd as nvd
+    from paper_2310_11222_amd import _abi
+    g1 = barabasi_albert(300, 2, np.random.default_rng(5))
+    b = nvd.Batch([dev_graph(g1)])
+    P = np.random.default_rng(6).random((300, 2))
+    ks, Pf, Qf = b.pack([P], [P * 0.5])
+    import ctypes as C
+    import torch
+    o = nvd.opts("mixed", 1e-8)
+    o.flags |= _abi.NVD_PRECOND_TREE
+    d = torch.empty(2, dtype=torch.float64, device="cuda")
+    st = _abi.load().nvd_batch_distances(b._h, ks.ctypes.data_as(C.c_void_p), Pf.data_ptr(),
+                                         Qf.data_ptr(), C.byref(o), d.data_ptr(), None, None, None)
+    assert st == _abi.NVD_E_UNSUPPORTED
