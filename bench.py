@@ -138,7 +138,9 @@ def bench_batched(steps, warmup):
 def bench_density():
     """Section 4.2 density sweep: |V| = 10^4, average degree 1..64 on ER, BA,
     WS and SBM, 8 pairs per graph, mixed precision to 1e-8 (the time of one
-    call after a warm-up call, and the largest CG iteration count)."""
+    call after a warm-up call, and the largest CG iteration count), with the
+    Jacobi diagonal and with the spanning-tree preconditioner (section 3.2;
+    the forest is built by the warm-up call)."""
     import torch
     import paper_2310_11222_amd as nvd
     from nvdgen import density_graph, DENSITY_MODELS, DENSITY_DEGREES
@@ -150,19 +152,22 @@ def bench_density():
             dg = nvd.Graph(g.row_ptr, g.col_idx, None)
             Pd = torch.as_tensor(P).cuda()
             Qd = torch.as_tensor(Q).cuda()
-            dg.distances(Pd, Qd, precision="mixed", rtol=1e-8)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, _, info = dg.distances(Pd, Qd, precision="mixed", rtol=1e-8)
-            torch.cuda.synchronize()
-            t = time.perf_counter() - t0
-            rows.append({"avg_degree": d, "ms_per_8": round(t * 1e3, 3),
-                         "iters": max(i["iters"] for i in info),
-                         "components": dg.stats()["n_comp"]})
+            row = {"avg_degree": d, "components": dg.stats()["n_comp"]}
+            for pre, key in (("jacobi", ""), ("tree", "tree_")):
+                dg.distances(Pd, Qd, precision="mixed", rtol=1e-8, precond=pre)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, info = dg.distances(Pd, Qd, precision="mixed", rtol=1e-8, precond=pre)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                row[key + "ms_per_8"] = round(t * 1e3, 3)
+                row[key + "converged"] = all(i["status"] == 0 for i in info)
+                row[key + "iters"] = max(i["iters"] for i in info)
+            rows.append(row)
             dg.close()
         out[model] = rows
-    log("density sweep (ms per 8 distances): " +
-        json.dumps({m: [r["ms_per_8"] for r in v] for m, v in out.items()}))
+    log("density sweep (ms per 8 distances, jacobi / tree): " +
+        json.dumps({m: [(r["ms_per_8"], r["tree_ms_per_8"]) for r in v] for m, v in out.items()}))
     return {"workload": "density_sweep_n1e4_deg1_to_64", "models": out}
 
 

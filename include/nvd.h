@@ -83,11 +83,18 @@ enum {
   NVD_WARM_START = 1u,      /* X_inout holds a starting guess on entry */
   NVD_BATCH_PERSISTENT = 2u,/* nvd_batch_distances: the single persistent
                                launch instead of the sweep solver */
-  NVD_PRECOND_TREE = 4u     /* nvd_distances / nvd_pairwise: precondition CG
+  NVD_PRECOND_TREE = 4u,    /* nvd_distances / nvd_pairwise: precondition CG
                                with a spanning forest of the graph (exact
                                tree solve, section 3.2 tree preconditioners)
                                instead of the Jacobi diagonal; for very sparse
                                graphs.  Not for batches. */
+  NVD_PRECOND_AUTO = 8u     /* nvd_distances / nvd_pairwise: the spanning
+                               forest when at most n/100 edges lie off it
+                               (m - n + c <= n / 100 for m edges and c
+                               components: tree PCG then needs at most that
+                               many iterations plus one in exact arithmetic),
+                               else the Jacobi diagonal.  Batches always use
+                               the Jacobi diagonal under this flag. */
 };
 
 typedef struct nvd_graph nvd_graph;
@@ -107,7 +114,8 @@ typedef struct nvd_opts {
   int32_t max_refine;  /* MIXED: outer refinement steps; default 30 */
   int32_t tile_k;      /* columns per SpMM pass: 1,2,4,8,16,32,64; 0 = the
                           library's autotuned choice */
-  uint32_t flags;      /* NVD_WARM_START, NVD_BATCH_PERSISTENT, NVD_PRECOND_TREE */
+  uint32_t flags;      /* NVD_WARM_START, NVD_BATCH_PERSISTENT, NVD_PRECOND_TREE,
+                          NVD_PRECOND_AUTO */
 } nvd_opts;
 
 typedef struct nvd_pair_info {

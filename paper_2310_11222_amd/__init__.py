@@ -62,8 +62,10 @@ def opts(precision="fp64", rtol=1e-10, inner_rtol=1e-5, max_iter=20000, max_refi
     o.flags = NVD_WARM_START if warm_start else 0
     if precond == "tree":
         o.flags |= _abi.NVD_PRECOND_TREE
+    elif precond == "auto":
+        o.flags |= _abi.NVD_PRECOND_AUTO
     elif precond != "jacobi":
-        raise ValueError("precond must be 'jacobi' or 'tree'")
+        raise ValueError("precond must be 'jacobi', 'tree' or 'auto'")
     return o
 
 
@@ -146,7 +148,10 @@ class Graph:
     def distances(self, P, Q, precision="fp64", rtol=1e-10, inner_rtol=1e-5, max_iter=20000,
                   max_refine=30, tile_k=0, return_x=False, X0=None, raise_on_noconv=False,
                   precond="jacobi"):
-        """Returns (d, X or None, info list).  P, Q: (n, k) or (n,) float64."""
+        """Returns (d, X or None, info list).  P, Q: (n, k) or (n,) float64.
+        precond: "jacobi" (the diagonal), "tree" (a spanning forest, solved
+        exactly) or "auto" (the forest when at most n/100 edges lie off it,
+        else the diagonal)."""
         torch = _torch()
         P = _as_dev64(P, "P")
         Q = _as_dev64(Q, "Q")

@@ -15,6 +15,7 @@ NVD_DT_F64, NVD_DT_F32 = 0, 1
 NVD_WARM_START = 1
 NVD_BATCH_PERSISTENT = 2
 NVD_PRECOND_TREE = 4
+NVD_PRECOND_AUTO = 8
 
 
 class NvdOpts(C.Structure):

@@ -274,7 +274,7 @@ nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double*
   sp.max_iter = o.max_iter;
   sp.max_refine = o.max_refine;
   sp.warm = (o.flags & NVD_WARM_START) != 0;
-  sp.tree = (o.flags & NVD_PRECOND_TREE) != 0;
+  sp.tree = use_tree(g, o.flags);
   int tile = o.tile_k;
   if (tile == 0) tile = choose_tile(g, k, o.precision, s);
   std::vector<nvd_pair_info> hinfo(k);

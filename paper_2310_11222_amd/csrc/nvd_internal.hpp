@@ -214,6 +214,9 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
 nvd_status project_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
                         double* Dbar, int64_t ldd, double* norms, hipStream_t s);
 // Tree preconditioner (tree.hip): set up for tiles up to T; z = L_T^+ r.
+// NVD_PRECOND_TREE, or NVD_PRECOND_AUTO on a graph with few edges off its
+// spanning forest.
+bool use_tree(const DevGraph* g, uint32_t flags);
 nvd_status ensure_tree(DevGraph* g, int T);
 nvd_status tree_solve(DevGraph* g, int prec, int T, const void* r, void* z, hipStream_t s);
 void free_tree(TreePre* tp);

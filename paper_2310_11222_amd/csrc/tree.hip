@@ -144,6 +144,15 @@ void free_tree(TreePre* tp) {
   delete tp;
 }
 
+bool use_tree(const DevGraph* g, uint32_t flags) {
+  if (flags & NVD_PRECOND_TREE) return true;
+  if (!(flags & NVD_PRECOND_AUTO)) return false;
+  // edges off a spanning forest: m - (n - c); each adds at most one PCG
+  // iteration to the tree's exact solve
+  const long off = (long)g->nnz / 2 - g->n + g->n_comp;
+  return off * 100 <= (long)g->n;
+}
+
 nvd_status ensure_tree(DevGraph* g, int T) {
   if (!g->tree) NVD_TRY(build_tree(g));
   TreePre* tp = g->tree;

@@ -115,6 +115,46 @@ def test_pairwise_with_tree_preconditioner():
     assert rel_err(D.cpu().numpy()[iu, ju], ref).max() <= 1e-8
 
 
+@pytest.mark.parametrize("model,deg,expect_tree", [("ws", 1, True), ("ba", 2, True), ("er", 2, False),
+                                                   ("ws", 4, False)])
+def test_auto_picks_tree_only_when_few_edges_lie_off_it(model, deg, expect_tree):
+    """precond="auto": the forest when m - n + c <= n/100, else the diagonal;
+    the iteration counts show which one ran."""
+    g, P, Q = density_graph(model, deg)
+    say("tree auto", model, deg)
+    dg = dev_graph(g)
+    st = dg.stats()
+    off = g.num_edges - g.n + st["n_comp"]
+    assert (off * 100 <= g.n) == expect_tree
+    runs = {}
+    for pre in ("jacobi", "tree", "auto"):
+        d, _, info = dg.distances(P, Q, precision="fp64", rtol=1e-10, precond=pre)
+        runs[pre] = (d.cpu().numpy(), [i["iters"] for i in info])
+    picked = "tree" if expect_tree else "jacobi"
+    assert runs["auto"][1] == runs[picked][1]
+    assert np.array_equal(runs["auto"][0], runs[picked][0])
+
+
+def test_batches_take_auto_as_jacobi():
+    import paper_2310_11222_amd as nvd
+    g1 = barabasi_albert(300, 1, np.random.default_rng(5))   # a tree
+    b = nvd.Batch([dev_graph(g1)])
+    P = np.random.default_rng(6).random((300, 2))
+    say("tree batch auto")
+    d, _, _ = b.distances([P], [P[::-1].copy()], precision="mixed", rtol=1e-8)
+    from paper_2310_11222_amd import _abi
+    import ctypes as C
+    import torch
+    ks, Pf, Qf = b.pack([P], [P[::-1].copy()])
+    o = nvd.opts("mixed", 1e-8)
+    o.flags |= _abi.NVD_PRECOND_AUTO
+    d2 = torch.empty(2, dtype=torch.float64, device="cuda")
+    st = _abi.load().nvd_batch_distances(b._h, ks.ctypes.data_as(C.c_void_p), Pf.data_ptr(),
+                                         Qf.data_ptr(), C.byref(o), d2.data_ptr(), None, None, None)
+    assert st == _abi.NVD_OK
+    assert np.array_equal(d2.cpu().numpy(), d.cpu().numpy())
+
+
 def test_batches_reject_tree_flag():
     import paper_2310_11222_amd as nvd
     from paper_2310_11222_amd import _abi
