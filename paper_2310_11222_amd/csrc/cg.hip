@@ -4,8 +4,10 @@
 //
 // Per CG iteration (per column c, preconditioner M = D):
 //   q = L p                 sigma = p^T q        alpha = rho / sigma   (SpMM, EPI_CG)
-//   x += alpha p; r -= alpha q; z = r / deg;  rho' = r^T z; ||r||^2   (k_update)
-//   beta = rho' / rho; p = z + beta p                                  (k_direction)
+//   r -= alpha q; z = r / deg;  rho' = r^T z; ||r||^2; beta = rho'/rho (k_update)
+//   x += alpha p; p = z + beta p                                       (k_direction)
+// x is updated where p is read anyway: 8 vector passes per iteration
+// instead of 9.
 // Every reduction finishes on the device (last block of the grid), so the
 // host only polls one word per chunk of iterations.
 //
@@ -150,6 +152,7 @@ __global__ __launch_bounds__(kBS) void k_proj_init(int n, long cap, ProjSrc src,
     cs->status[t] = kStOk;
     cs->itol2[t] = 0.0;
   }
+  if (t == 0) cs->xseq = cs->xdone = 0;   // a CG run starts: no x update pending
   recount_active(cs, T);
 }
 
@@ -175,13 +178,13 @@ __device__ __forceinline__ void invd_of(const V* __restrict__ invd, int n, long 
   }
 }
 
-// x += alpha p; r -= alpha q; rho' = r^T D^-1 r; ||r||^2.  The grid's last
-// block forms beta and retires converged columns.  TREE (spanning-tree
-// preconditioner): ||r||^2 and retirement only; rho' = r^T z and beta follow
-// once z = L_T^+ r is known (k_rz).
+// r -= alpha q; rho' = r^T D^-1 r; ||r||^2.  The grid's last block forms
+// beta, retires converged columns and advances xseq (x += alpha p of this
+// iteration is left to the direction kernel, which reads p anyway).  TREE
+// (spanning-tree preconditioner): ||r||^2 and retirement only; rho' = r^T z
+// and beta follow once z = L_T^+ r is known (k_rz).
 template <typename V, int T, bool TREE = false>
-__global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__ x,
-                                                V* __restrict__ r, const V* __restrict__ p,
+__global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__ r,
                                                 const V* __restrict__ q,
                                                 const V* __restrict__ invd, double rtol2,
                                                 int max_iter, ColState* cs, GridRed red) {
@@ -189,7 +192,11 @@ __global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__
   constexpr int N = Vec16<V>::N;
   __shared__ double sh[2 * kBS * N];
   __shared__ double vals[2 * kMaxTile];
-  if (cs->n_active == 0) return;
+  if (cs->n_active == 0) {
+    // no iteration ran: the direction kernel that follows has no x to update
+    if (blockIdx.x == 0 && threadIdx.x == 0) cs->xdone = cs->xseq;
+    return;
+  }
   const int t = threadIdx.x;
   V al[N];
 #pragma unroll
@@ -199,25 +206,19 @@ __global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__
   for (int v = 0; v < N; ++v) acc[0][v] = acc[1][v] = 0.0;
   const long nv = cap / N;
   for (long i = (long)blockIdx.x * kBS + t; i < nv; i += (long)gridDim.x * kBS) {
-    VT xv = reinterpret_cast<const VT*>(x)[i];
     VT rv = reinterpret_cast<const VT*>(r)[i];
-    const VT pv = reinterpret_cast<const VT*>(p)[i];
     const VT qv = reinterpret_cast<const VT*>(q)[i];
-    V* xs = reinterpret_cast<V*>(&xv);
     V* rs = reinterpret_cast<V*>(&rv);
-    const V* ps = reinterpret_cast<const V*>(&pv);
     const V* qs = reinterpret_cast<const V*>(&qv);
     V iv[N];
     if constexpr (!TREE) invd_of<V, T>(invd, n, i, iv);
 #pragma unroll
     for (int v = 0; v < N; ++v) {
-      xs[v] += al[v] * ps[v];
       rs[v] -= al[v] * qs[v];
       const double rd = (double)rs[v];
       if constexpr (!TREE) acc[0][v] += rd * rd * (double)iv[v];
       acc[1][v] += rd * rd;
     }
-    reinterpret_cast<VT*>(x)[i] = xv;
     reinterpret_cast<VT*>(r)[i] = rv;
   }
   block_reduce_cols<kBS, 2, N>(acc, T, sh);
@@ -262,34 +263,52 @@ __global__ __launch_bounds__(kBS) void k_update(int n, long cap, V* __restrict__
     double wmax = 0.0;
     for (int c = 0; c < T; ++c) wmax = vals[c] > wmax ? vals[c] : wmax;
     cs->worst = wmax;
+    cs->xseq += 1;
   }
   recount_active(cs, T);
 }
 
-// p = D^-1 r + beta p
+// x += alpha p (the iteration whose update kernel ran, columns that retired
+// in it included; alpha is 0 on columns inactive at the apply), then
+// p = D^-1 r + beta p while any column is active.
 template <typename V, int T>
-__global__ __launch_bounds__(kBS) void k_direction(int n, long cap, V* __restrict__ p,
-                                                   const V* __restrict__ r,
+__global__ __launch_bounds__(kBS) void k_direction(int n, long cap, V* __restrict__ x,
+                                                   V* __restrict__ p, const V* __restrict__ r,
                                                    const V* __restrict__ invd,
                                                    const ColState* cs) {
   using VT = typename Vec16<V>::type;
   constexpr int N = Vec16<V>::N;
-  if (cs->n_active == 0) return;
+  const bool xup = cs->xseq != cs->xdone;
+  const bool pup = cs->n_active != 0;
+  if (!xup && !pup) return;
   const int t = threadIdx.x;
-  V be[N];
+  V al[N], be[N];
 #pragma unroll
-  for (int v = 0; v < N; ++v) be[v] = (V)cs->beta[(t * N + v) % T];
+  for (int v = 0; v < N; ++v) {
+    al[v] = (V)cs->alpha[(t * N + v) % T];
+    be[v] = (V)cs->beta[(t * N + v) % T];
+  }
   const long nv = cap / N;
   for (long i = (long)blockIdx.x * kBS + t; i < nv; i += (long)gridDim.x * kBS) {
     VT pv = reinterpret_cast<const VT*>(p)[i];
-    const VT rv = reinterpret_cast<const VT*>(r)[i];
-    V* ps = reinterpret_cast<V*>(&pv);
-    const V* rs = reinterpret_cast<const V*>(&rv);
-    V iv[N];
-    invd_of<V, T>(invd, n, i, iv);
+    const V* ps = reinterpret_cast<const V*>(&pv);
+    if (xup) {
+      VT xv = reinterpret_cast<const VT*>(x)[i];
+      V* xs = reinterpret_cast<V*>(&xv);
 #pragma unroll
-    for (int v = 0; v < N; ++v) ps[v] = rs[v] * iv[v] + be[v] * ps[v];
-    reinterpret_cast<VT*>(p)[i] = pv;
+      for (int v = 0; v < N; ++v) xs[v] += al[v] * ps[v];
+      reinterpret_cast<VT*>(x)[i] = xv;
+    }
+    if (pup) {
+      const VT rv = reinterpret_cast<const VT*>(r)[i];
+      V* pw = reinterpret_cast<V*>(&pv);
+      const V* rs = reinterpret_cast<const V*>(&rv);
+      V iv[N];
+      invd_of<V, T>(invd, n, i, iv);
+#pragma unroll
+      for (int v = 0; v < N; ++v) pw[v] = rs[v] * iv[v] + be[v] * pw[v];
+      reinterpret_cast<VT*>(p)[i] = pv;
+    }
   }
 }
 
@@ -353,26 +372,41 @@ __global__ __launch_bounds__(kBS) void k_rz(long cap, const V* __restrict__ r, c
   recount_active(cs, T);
 }
 
-// p = z + beta p (z = L_T^+ r)
+// x += alpha p as in k_direction, then p = z + beta p (z = L_T^+ r)
 template <typename V, int T>
-__global__ __launch_bounds__(kBS) void k_direction_z(long cap, V* __restrict__ p,
+__global__ __launch_bounds__(kBS) void k_direction_z(long cap, V* __restrict__ x, V* __restrict__ p,
                                                      const V* __restrict__ z, const ColState* cs) {
   using VT = typename Vec16<V>::type;
   constexpr int N = Vec16<V>::N;
-  if (cs->n_active == 0) return;
+  const bool xup = cs->xseq != cs->xdone;
+  const bool pup = cs->n_active != 0;
+  if (!xup && !pup) return;
   const int t = threadIdx.x;
-  V be[N];
+  V al[N], be[N];
 #pragma unroll
-  for (int v = 0; v < N; ++v) be[v] = (V)cs->beta[(t * N + v) % T];
+  for (int v = 0; v < N; ++v) {
+    al[v] = (V)cs->alpha[(t * N + v) % T];
+    be[v] = (V)cs->beta[(t * N + v) % T];
+  }
   const long nv = cap / N;
   for (long i = (long)blockIdx.x * kBS + t; i < nv; i += (long)gridDim.x * kBS) {
     VT pv = reinterpret_cast<const VT*>(p)[i];
-    const VT zv = reinterpret_cast<const VT*>(z)[i];
-    V* ps = reinterpret_cast<V*>(&pv);
-    const V* zs = reinterpret_cast<const V*>(&zv);
+    const V* ps = reinterpret_cast<const V*>(&pv);
+    if (xup) {
+      VT xv = reinterpret_cast<const VT*>(x)[i];
+      V* xs = reinterpret_cast<V*>(&xv);
 #pragma unroll
-    for (int v = 0; v < N; ++v) ps[v] = zs[v] + be[v] * ps[v];
-    reinterpret_cast<VT*>(p)[i] = pv;
+      for (int v = 0; v < N; ++v) xs[v] += al[v] * ps[v];
+      reinterpret_cast<VT*>(x)[i] = xv;
+    }
+    if (pup) {
+      const VT zv = reinterpret_cast<const VT*>(z)[i];
+      V* pw = reinterpret_cast<V*>(&pv);
+      const V* zs = reinterpret_cast<const V*>(&zv);
+#pragma unroll
+      for (int v = 0; v < N; ++v) pw[v] = zs[v] + be[v] * pw[v];
+      reinterpret_cast<VT*>(p)[i] = pv;
+    }
   }
 }
 
@@ -444,6 +478,7 @@ __global__ __launch_bounds__(kBS) void k_inner_init_any(int T, int n, long cap, 
     cs->alpha[t] = 0.0;
     cs->beta[t] = 0.0;
   }
+  if (t == 0) cs->xseq = cs->xdone = 0;
   recount_active(cs, T);
 }
 
@@ -519,6 +554,7 @@ __global__ __launch_bounds__(kBS) void k_restart(int n, long cap, const double* 
     cs->alpha[t] = 0.0;
     cs->beta[t] = 0.0;
   }
+  if (t == 0) cs->xseq = cs->xdone = 0;
   recount_active(cs, T);
 }
 
@@ -683,8 +719,8 @@ static nvd_status cg_loop(DevGraph* g, Workspace* ws, int T, V* x, V* r, V* p, V
   sc.cs = ws->cs;
   sc.epi = EPI_CG;
   const double sv = (double)sizeof(V);
-  const double upd_bytes = (6.0 * T * sv + sv) * g->n;   // x, r, p, q in; x, r out; 1/deg
-  const double dir_bytes = (3.0 * T * sv + sv) * g->n;   // r, p in; p out; 1/deg
+  const double upd_bytes = (3.0 * T * sv + sv) * g->n;   // r, q in; r out; 1/deg
+  const double dir_bytes = (5.0 * T * sv + sv) * g->n;   // x, r, p in; x, p out; 1/deg
   // Iterations are enqueued in chunks; after each chunk the host reads four
   // words (active count, largest iteration count, worst residual ratio) and
   // sizes the next chunk from the observed decay of the worst residual, so
@@ -704,9 +740,9 @@ static nvd_status cg_loop(DevGraph* g, Workspace* ws, int T, V* x, V* r, V* p, V
       int pid = prof_begin(s, sizeof(V) == 8 ? PK_UPD64 : PK_UPD32, upd_bytes);
       if (sp.tree) {
         NVD_TILE_SWITCH(T, (k_update<V, TT, true><<<sgrid, kBS, 0, s>>>(
-                               g->n, cap, x, r, p, q, invd, rtol2, max_iter, ws->cs, ws->red)));
+                               g->n, cap, r, q, invd, rtol2, max_iter, ws->cs, ws->red)));
       } else {
-        NVD_TILE_SWITCH(T, (k_update<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, x, r, p, q, invd, rtol2,
+        NVD_TILE_SWITCH(T, (k_update<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, r, q, invd, rtol2,
                                                                   max_iter, ws->cs, ws->red)));
       }
       prof_end(s, pid);
@@ -716,9 +752,9 @@ static nvd_status cg_loop(DevGraph* g, Workspace* ws, int T, V* x, V* r, V* p, V
         // z = L_T^+ r into q (free until the next apply), then beta and p
         NVD_TRY(tree_solve(g, sizeof(V) == 8 ? 0 : 1, T, r, q, s));
         NVD_TILE_SWITCH(T, (k_rz<V, TT, 1><<<sgrid, kBS, 0, s>>>(cap, r, q, ws->cs, ws->red)));
-        NVD_TILE_SWITCH(T, (k_direction_z<V, TT><<<sgrid, kBS, 0, s>>>(cap, p, q, ws->cs)));
+        NVD_TILE_SWITCH(T, (k_direction_z<V, TT><<<sgrid, kBS, 0, s>>>(cap, x, p, q, ws->cs)));
       } else {
-        NVD_TILE_SWITCH(T, (k_direction<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, p, r, invd, ws->cs)));
+        NVD_TILE_SWITCH(T, (k_direction<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, x, p, r, invd, ws->cs)));
       }
       prof_end(s, pid);
       ids.push_back(pid);
@@ -773,6 +809,7 @@ __global__ void k_tune_state(int T, ColState* cs) {
     cs->n_active = T;
     cs->n_oactive = T;
     cs->it_max = 0;
+    cs->xseq = cs->xdone = 0;
   }
 }
 
@@ -810,9 +847,9 @@ static nvd_status enqueue_tune_iteration(DevGraph* g, Workspace* ws, int T, int 
   sc.cs = tcs;
   sc.epi = EPI_PLAIN;
   NVD_TRY(launch_spmm(sc, ws->red, s));
-  NVD_TILE_SWITCH(T, (k_update<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, x, r, p, q, invd, 1.0,
+  NVD_TILE_SWITCH(T, (k_update<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, r, q, invd, 1.0,
                                                             0x7fffffff, tcs, ws->red)));
-  NVD_TILE_SWITCH(T, (k_direction<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, p, r, invd, tcs)));
+  NVD_TILE_SWITCH(T, (k_direction<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, x, p, r, invd, tcs)));
   NVD_HIP(hipGetLastError());
   return NVD_OK;
 }

@@ -58,6 +58,11 @@ struct ColState {
   int it_max;               // largest it_cur[] over the tile
   int pad;
   double worst;             // largest rr / (rtol^2 bnorm2) over active columns
+  // x += alpha p is applied by the direction kernel, for the iteration whose
+  // update kernel ran: that kernel's last block advances xseq, and an update
+  // kernel that found nothing active sets xdone = xseq instead.
+  int xseq;
+  int xdone;
 };
 
 // Two-level, fixed-order grid reduction scratch.
