@@ -50,6 +50,11 @@ struct SState {
   int* g_oact;       // graph has a pair not yet converged
   int* n_act;        // [2]: totals of act and oact (polled by the host)
   unsigned* tick;    // per-graph chunk arrival counters
+  // c += alpha p runs in ks_direction for the iteration whose ks_update ran
+  // on the graph: the graph's last chunk there advances xseq; a ks_update
+  // that finds the graph inactive (and ks_accum) set xdone = xseq.
+  int* xseq;
+  int* xdone;
 };
 
 struct SArgs {
@@ -206,6 +211,8 @@ __global__ void ks_reset(SArgs a) {
   if (i < a.G) {
     a.s.g_act[i] = 0;
     a.s.g_oact[i] = 0;
+    a.s.xseq[i] = 0;
+    a.s.xdone[i] = 0;
   }
   if (i < 2) a.s.n_act[i] = 0;
 }
@@ -563,7 +570,8 @@ __global__ __launch_bounds__(SBS) void ks_inner_init(SArgs a, int first_step) {
   }
 }
 
-// c += alpha p; r -= alpha q; rho' = r^T D^-1 r, ||r||^2 -> beta, convergence
+// r -= alpha q; rho' = r^T D^-1 r, ||r||^2 -> beta, convergence (c += alpha p
+// is left to ks_direction, which reads p anyway)
 template <typename V, int T>
 __global__ __launch_bounds__(SBS) void ks_update(SArgs a) {
   using SV = SVec<V, T>;
@@ -578,14 +586,17 @@ __global__ __launch_bounds__(SBS) void ks_update(SArgs a) {
     const int hi = a.ch_hi[ch];
     if (hi < 0) continue;
     const int g = a.ch_graph[ch];
-    if (!a.s.g_act[g]) continue;
+    if (!a.s.g_act[g]) {
+      // no iteration on this graph: nothing for ks_direction to add to c
+      // (the graph's first chunk is a row chunk)
+      if (ch == a.sg[g].first && t == 0) a.s.xdone[g] = a.s.xseq[g];
+      continue;
+    }
     const SGraph sg = a.sg[g];
     const int lo = a.ch_lo[ch];
     const long vo = sg.node_off * T;
-    const VT* P4 = reinterpret_cast<const VT*>(reinterpret_cast<const V*>(a.pv) + vo);
     const VT* Q4 = reinterpret_cast<const VT*>(reinterpret_cast<const V*>(a.qv) + vo);
     VT* R4 = reinterpret_cast<VT*>(reinterpret_cast<V*>(a.rv) + vo);
-    VT* C4 = reinterpret_cast<VT*>(reinterpret_cast<V*>(a.cv) + vo);
     const V* invd = invd_all + sg.node_off;
     V al[NE];
 #pragma unroll
@@ -595,20 +606,16 @@ __global__ __launch_bounds__(SBS) void ks_update(SArgs a) {
     for (int v = 0; v < NE; ++v) acc[0][v] = acc[1][v] = 0.0;
     const long i1 = (long)hi * T / NE;
     for (long i = (long)lo * T / NE + t; i < i1; i += SBS) {
-      V p[NE], q[NE], r[NE], cc[NE];
-      unpack<V, NE>(P4[i], p);
+      V q[NE], r[NE];
       unpack<V, NE>(Q4[i], q);
       unpack<V, NE>(R4[i], r);
-      unpack<V, NE>(C4[i], cc);
 #pragma unroll
       for (int v = 0; v < NE; ++v) {
-        cc[v] += al[v] * p[v];
         r[v] -= al[v] * q[v];
         const double rd = (double)r[v];
         acc[0][v] += rd * rd * (double)invd[(i * NE + v) / T];
         acc[1][v] += rd * rd;
       }
-      C4[i] = pack<V, NE>(cc);
       R4[i] = pack<V, NE>(r);
     }
     chunk_block_sum<2, NE>(acc, T, sh, vals);
@@ -635,13 +642,16 @@ __global__ __launch_bounds__(SBS) void ks_update(SArgs a) {
         }
         a.s.beta[i] = be;
       }
+      if (t == 0) a.s.xseq[g] += 1;
       recount_graph(a, g);
     }
     __syncthreads();
   }
 }
 
-// p = D^-1 r + beta p
+// c += alpha p on graphs whose ks_update ran this iteration (columns that
+// retired in it included; alpha is 0 on columns inactive at the apply), then
+// p = D^-1 r + beta p on graphs still active.
 template <typename V, int T>
 __global__ __launch_bounds__(SBS) void ks_direction(SArgs a) {
   using SV = SVec<V, T>;
@@ -653,24 +663,40 @@ __global__ __launch_bounds__(SBS) void ks_direction(SArgs a) {
     const int hi = a.ch_hi[ch];
     if (hi < 0) continue;
     const int g = a.ch_graph[ch];
-    if (!a.s.g_act[g]) continue;
+    const bool xup = a.s.xseq[g] != a.s.xdone[g];
+    const bool pup = a.s.g_act[g] != 0;
+    if (!xup && !pup) continue;
     const SGraph sg = a.sg[g];
     const int lo = a.ch_lo[ch];
     const long vo = sg.node_off * T;
     VT* P4 = reinterpret_cast<VT*>(reinterpret_cast<V*>(a.pv) + vo);
+    VT* C4 = reinterpret_cast<VT*>(reinterpret_cast<V*>(a.cv) + vo);
     const VT* R4 = reinterpret_cast<const VT*>(reinterpret_cast<const V*>(a.rv) + vo);
     const V* invd = invd_all + sg.node_off;
-    V be[NE];
+    V al[NE], be[NE];
 #pragma unroll
-    for (int v = 0; v < NE; ++v) be[v] = (V)a.s.beta[g * T + (t * NE + v) % T];
+    for (int v = 0; v < NE; ++v) {
+      al[v] = (V)a.s.alpha[g * T + (t * NE + v) % T];
+      be[v] = (V)a.s.beta[g * T + (t * NE + v) % T];
+    }
     const long i1 = (long)hi * T / NE;
     for (long i = (long)lo * T / NE + t; i < i1; i += SBS) {
-      V p[NE], r[NE];
+      V p[NE];
       unpack<V, NE>(P4[i], p);
-      unpack<V, NE>(R4[i], r);
+      if (xup) {
+        V cc[NE];
+        unpack<V, NE>(C4[i], cc);
 #pragma unroll
-      for (int v = 0; v < NE; ++v) p[v] = r[v] * invd[(i * NE + v) / T] + be[v] * p[v];
-      P4[i] = pack<V, NE>(p);
+        for (int v = 0; v < NE; ++v) cc[v] += al[v] * p[v];
+        C4[i] = pack<V, NE>(cc);
+      }
+      if (pup) {
+        V r[NE];
+        unpack<V, NE>(R4[i], r);
+#pragma unroll
+        for (int v = 0; v < NE; ++v) p[v] = r[v] * invd[(i * NE + v) / T] + be[v] * p[v];
+        P4[i] = pack<V, NE>(p);
+      }
     }
   }
 }
@@ -684,6 +710,8 @@ __global__ __launch_bounds__(SBS) void ks_accum(SArgs a) {
     const int hi = a.ch_hi[ch];
     if (hi < 0) continue;
     const int g = a.ch_graph[ch];
+    // the inner loop is over: every c += alpha p has been applied
+    if (ch == a.sg[g].first && t == 0) a.s.xdone[g] = a.s.xseq[g];
     if (!a.s.g_oact[g]) continue;
     const SGraph sg = a.sg[g];
     const int lo = a.ch_lo[ch];
@@ -874,7 +902,7 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
     b->spart_cap = need_part;
   }
   const size_t GT = (size_t)G * T;
-  const size_t state_bytes = GT * (8 * sizeof(double) + 6 * sizeof(int)) + (size_t)G * 3 * sizeof(int) +
+  const size_t state_bytes = GT * (8 * sizeof(double) + 6 * sizeof(int)) + (size_t)G * 5 * sizeof(int) +
                              2 * sizeof(int) + 64;
   if (b->sstate_cap < state_bytes) {
     if (b->sstate) (void)hipFree(b->sstate);
@@ -967,6 +995,8 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
     a.s.g_act = take_i(G);
     a.s.g_oact = take_i(G);
     a.s.tick = reinterpret_cast<unsigned*>(take_i(G));
+    a.s.xseq = take_i(G);
+    a.s.xdone = take_i(G);
     a.s.n_act = take_i(2);
   }
   a.P = P;
