@@ -411,8 +411,11 @@ __global__ __launch_bounds__(kBS) void k_direction_z(long cap, V* __restrict__ x
 }
 
 // Inner (FP32) solve set-up from an FP64 vector src (the outer residual or
-// delta_bar): rbar = src - mean (FP64), r32 = rbar, p32 = D^-1 r32,
-// x32 = q32 = 0.
+// delta_bar): rbar = src - mean (FP64), r32 = rbar, p32 = D^-1 r32, x32 = 0,
+// and q32 = 0 on the padding past n*T (the apply writes every row below n
+// before q is read).  Four consecutive elements per thread, moved as 16-byte
+// vectors; the grid stride is a multiple of T, so a thread's four columns
+// stay the same throughout.
 // The last block checks outer convergence on ||rbar|| (FP64) and starts the
 // inner CG on the pairs that are still open.
 __global__ __launch_bounds__(kBS) void k_inner_init_any(int T, int n, long cap, const double* src,
@@ -420,34 +423,48 @@ __global__ __launch_bounds__(kBS) void k_inner_init_any(int T, int n, long cap, 
                                                         float* r32, float* p32, float* q32,
                                                         double rtol2, double irtol2, int max_refine,
                                                         int first, ColState* cs, GridRed red) {
-  __shared__ double sh[3 * kBS];
+  constexpr int NE = 4;
+  __shared__ double sh[3 * kBS * NE];
   __shared__ double vals[3 * kMaxTile];
   const int t = threadIdx.x;
-  double acc[3][1] = {{0.0}, {0.0}, {0.0}};
-  for (long e = (long)blockIdx.x * kBS + t; e < cap; e += (long)gridDim.x * kBS) {
-    const long i = e / T;
-    const int c = (int)(e % T);
-    float f = 0.0f;
-    float z = 0.0f;
-    if (i < n) {
-      const double v = src[e] - mean_of(m, i, c);
-      f = (float)v;
-      z = f * invd32[i];
-      acc[0][0] += v * v;
-      const double fd = (double)f;
-      acc[1][0] += fd * (double)z;
-      acc[2][0] += fd * fd;
+  double acc[3][NE];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int j = 0; j < NE; ++j) acc[d][j] = 0.0;
+  const long nT = (long)n * T;
+  const long nq = cap / NE;                 // cap is a multiple of 16
+  for (long qd = (long)blockIdx.x * kBS + t; qd < nq; qd += (long)gridDim.x * kBS) {
+    const double2 s01 = reinterpret_cast<const double2*>(src)[2 * qd];
+    const double2 s23 = reinterpret_cast<const double2*>(src)[2 * qd + 1];
+    const double sv[NE] = {s01.x, s01.y, s23.x, s23.y};
+    float f[NE], z[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      const long e = qd * NE + j;
+      f[j] = 0.0f;
+      z[j] = 0.0f;
+      if (e < nT) {
+        const long i = e / T;
+        const double v = sv[j] - mean_of(m, i, (int)(e % T));
+        f[j] = (float)v;
+        z[j] = f[j] * invd32[i];             // p0 = z0 = D^-1 r0
+        acc[0][j] += v * v;
+        const double fd = (double)f[j];
+        acc[1][j] += fd * (double)z[j];
+        acc[2][j] += fd * fd;
+      }
     }
-    r32[e] = f;
-    x32[e] = 0.0f;
-    p32[e] = z;                              // p0 = z0 = D^-1 r0
-    q32[e] = 0.0f;
+    reinterpret_cast<float4*>(r32)[qd] = make_float4(f[0], f[1], f[2], f[3]);
+    reinterpret_cast<float4*>(x32)[qd] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    reinterpret_cast<float4*>(p32)[qd] = make_float4(z[0], z[1], z[2], z[3]);
+    if (qd * NE + NE > nT) reinterpret_cast<float4*>(q32)[qd] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
-  block_reduce_cols<kBS, 3, 1>(acc, T, sh);
+  block_reduce_cols<kBS, 3, NE>(acc, T, sh);
   if (t < T) {
     vals[t] = sh[t];
-    vals[T + t] = sh[kBS + t];
-    vals[2 * T + t] = sh[2 * kBS + t];
+    vals[T + t] = sh[kBS * NE + t];
+    vals[2 * T + t] = sh[2 * kBS * NE + t];
   }
   __syncthreads();
   if (!grid_reduce<kBS>(vals, 3 * T, red)) return;
