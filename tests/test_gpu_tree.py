@@ -104,6 +104,54 @@ def test_general_weighted_disconnected_graph(precision, rtol, tol):
     assert all(i["status"] == 0 for i in info)
 
 
+@pytest.mark.parametrize("tile", [1, 2, 4, 8, 16, 32, 64])
+def test_tree_every_tile_width(tile):
+    """The tour scans split each chunk over 256/T lanes per column: every
+    tile width, on a weighted forest with a cycle, a path and isolated nodes
+    (several components, ragged last scan chunk), against the dense oracle."""
+    rng = np.random.default_rng(11)
+    t = random_tree(1500, rng, rng.uniform(0.3, 3.0, 1499))
+    n = t.n + 700 + 3
+    path_u = np.arange(t.n, t.n + 699)
+    eu = np.concatenate([t.eu, path_u, [t.n + 10]])
+    ev = np.concatenate([t.ev, path_u + 1, [t.n + 500]])          # one extra edge: a cycle
+    ew = np.concatenate([t.ew, rng.uniform(0.5, 2.0, 700)])
+    g = Graph(n, np.minimum(eu, ev), np.maximum(eu, ev), ew)
+    k = max(tile, 3) if tile < 64 else 64
+    P = rng.random((n, k))
+    Q = np.where(rng.random((n, k)) < 0.3, rng.random((n, k)), 0.0)
+    say("tree tile", tile)
+    dg = dev_graph(g)
+    ref = oracle.ge_dense(g.n, g.row_ptr, g.col_idx, g.w, P, Q)["d"]
+    for precision, rtol, tol in PREC:
+        d, _, info = dg.distances(P, Q, precision=precision, rtol=rtol, precond="tree", tile_k=tile)
+        assert rel_err(d.cpu().numpy(), ref).max() <= tol, (precision, tile)
+        assert all(i["status"] == 0 for i in info)
+
+
+@pytest.mark.parametrize("n,edges", [(1, []), (2, []), (2, [(0, 1)]), (5, []), (3, [(0, 2)])])
+def test_tree_degenerate_graphs(n, edges):
+    """A single node, edgeless graphs, one edge, an isolated node beside an
+    edge, with the tree preconditioner, against the dense oracle (0 where
+    the difference is constant on every component)."""
+    eu = np.array([e[0] for e in edges], dtype=np.int64)
+    ev = np.array([e[1] for e in edges], dtype=np.int64)
+    g = Graph(n, eu, ev)
+    rng = np.random.default_rng(n + len(edges))
+    P = rng.random((n, 3))
+    Q = rng.random((n, 3))
+    say("tree degenerate", n, edges)
+    dg = dev_graph(g)
+    ref = oracle.ge_dense(g.n, g.row_ptr, g.col_idx, g.w, P, Q)["d"]
+    for precision, rtol, tol in PREC:
+        d, _, info = dg.distances(P, Q, precision=precision, rtol=rtol, precond="tree")
+        d = d.cpu().numpy()
+        big = ref > 1e-12
+        assert np.all(d[~big] <= 1e-12), (precision, d, ref)
+        assert rel_err(d[big], ref[big]).max(initial=0.0) <= tol, (precision, d, ref)
+        assert all(i["status"] == 0 for i in info)
+
+
 def test_pairwise_with_tree_preconditioner():
     g, P, _ = density_graph("ws", 2)
     V = P[:, :6]
