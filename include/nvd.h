@@ -71,7 +71,7 @@ typedef enum nvd_status {
   NVD_E_BREAKDOWN = 5,   /* at least one pair lost positivity (p^T L p <= 0) */
   NVD_E_DEVICE = 6,      /* a HIP call failed */
   NVD_E_NOMEM = 7,       /* device allocation failed */
-  NVD_E_UNSUPPORTED = 8  /* valid request beyond this build's limits */
+  NVD_E_UNSUPPORTED = 8  /* valid request beyond the library's limits */
 } nvd_status;
 
 /* nvd_opts.precision */

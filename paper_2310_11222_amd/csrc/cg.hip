@@ -665,7 +665,7 @@ __global__ __launch_bounds__(kBS) void k_proj_out(int n, ProjSrc src, MeanSrc m,
 }
 
 // ---------------------------------------------------------------------------
-// host driver
+// host side
 // ---------------------------------------------------------------------------
 #define NVD_TILE_SWITCH(T, CALL)             \
   switch (T) {                               \

@@ -186,7 +186,7 @@ static nvd_status build_graph(int64_t n64, int64_t nnz64, const int64_t* row_ptr
     return NVD_E_ARG;
   }
   if (n64 >= INT32_MAX || nnz64 >= INT32_MAX) {
-    set_error("nvd_graph_create: n and nnz must be below 2^31 in this build");
+    set_error("nvd_graph_create: n and nnz must be below 2^31 (int32 indices)");
     return NVD_E_UNSUPPORTED;
   }
   if (!row_ptr || (nnz64 > 0 && !col_idx)) {

@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped (not failed) on a machine without a GPU so that a
-    # plain `pytest` run on the CPU stays green; `-m gpu` on the GPU machine runs them.
+    # plain `pytest` run on the CPU stays green; `-m gpu` on an MI355X runs them.
     try:
         import torch
         have_gpu = torch.cuda.is_available()
