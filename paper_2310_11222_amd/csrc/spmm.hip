@@ -23,7 +23,9 @@
 //  * long rows: segments of at most kSeg neighbours, one 256-thread block per
 //    segment, partial sums reduced in LDS; rows with several segments combine
 //    them in fixed order in the last segment block to arrive (per-row arrival
-//    counter), so results do not depend on timing.
+//    counter), so results do not depend on timing.  (One wave per segment
+//    was measured slower: at T = 32 a wave has a quarter of a block's
+//    neighbour slots, and the longest hub segment sets the kernel's time.)
 // The CSR and the output are touched once per pass and are loaded and stored
 // non-temporally.
 // Epilogues fuse the consumer of L X:
@@ -407,10 +409,14 @@ int spmm_max_nl(int prec, int T) {
 }
 
 // Default neighbour sub-groups per row: one (a lane group walks the whole
-// neighbour list of its row).
+// neighbour list of its row); build-time knob, capped by the lane budget.
+#ifndef NVD_DEFAULT_NL
+#define NVD_DEFAULT_NL 1
+#endif
 int default_nl(int T) {
-  (void)T;
-  return 1;
+  int nl = NVD_DEFAULT_NL;
+  while (nl > 1 && nl > spmm_max_nl(1, T)) nl >>= 1;
+  return nl;
 }
 
 static int short_grid(int n, int rows_per_step) {
@@ -449,12 +455,16 @@ static nvd_status launch_typed(const SpmmCall& c, const GridRed& red, hipStream_
   k.b = c.b;
   k.ldb = c.ldb;
   k.cs = c.cs;
-  const int nl = c.nl > 0 ? c.nl : default_nl(c.T);
+  int nl = c.nl > 0 ? c.nl : default_nl(c.T);
   // vector accesses need aligned rows of X, Y (and B)
   const int W16 = 16 / (int)sizeof(V);
   const int vw = c.T < W16 ? c.T : W16;
   bool vec = vec_rows(c.x, c.ldx, sizeof(V), vw) && vec_rows(c.y, c.ldy, sizeof(V), vw);
   if (c.epi == EPI_RESID) vec = vec && vec_rows(c.b, c.ldb, sizeof(double), vw);
+  // the neighbour sub-groups were tuned for one element type and alignment
+  // (the mixed solver's FP64 residual pass reuses the FP32 choice): halve
+  // them until a row's lane group fits in a wave
+  while (nl > 1 && rows_per_block<V>(c.T, nl, vec) == 0) nl >>= 1;
   const int rpb = rows_per_block<V>(c.T, nl, vec);
   if (rpb == 0) {
     set_error("spmm: unsupported tile/lane configuration T=" + std::to_string(c.T) +
