@@ -173,6 +173,78 @@ def bench_density():
     return {"workload": "density_sweep_n1e4_deg1_to_64", "models": out}
 
 
+def bench_spmv(calib_copy=False):
+    """The reference SpMV loads for the HBM claim: Y = L X on the 10^7-node
+    power-law configuration-model graph (unit weights), k = 1 and 16 columns,
+    FP32 and FP64, 100 back-to-back launches each (time per launch from HIP
+    events around the 100).  Algorithmic bytes: 4 nnz + 4 (n+1) + 2 k s n."""
+    import numpy as np
+    import torch
+    import paper_2310_11222_amd as nvd
+    from nvdgen import workload
+    t0 = time.perf_counter()
+    w = workload(5)
+    g = w.graphs[0]
+    log(f"spmv graph: n={g.n} nnz={g.nnz} gen {time.perf_counter() - t0:.1f}s")
+    dg = nvd.Graph(g.row_ptr, g.col_idx, None)
+    if calib_copy:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    rows = []
+    for k, dt, name in ((1, torch.float32, "f32"), (1, torch.float64, "f64"),
+                        (16, torch.float32, "f32"), (16, torch.float64, "f64")):
+        X = torch.rand(g.n, k, dtype=dt, device="cuda", generator=gen)
+        Y = torch.empty_like(X)
+        for _ in range(5):
+            dg.laplacian_apply(X, out=Y)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(100):
+            dg.laplacian_apply(X, out=Y)
+        b.record()
+        b.synchronize()
+        us = a.elapsed_time(b) / 100 * 1e3
+        alg = 4.0 * g.nnz + 4.0 * (g.n + 1) + 2.0 * k * X.element_size() * g.n
+        rows.append({"k": k, "dtype": name, "us_per_launch": round(us, 1),
+                     "algorithmic_bytes": alg, "achieved_gbs": round(alg / us / 1e3, 1),
+                     "frac": round(alg / us / 1e3 / HBM_PEAK_GBS, 4)})
+        del X, Y
+    dg.close()
+    res = {"workload": "config_model_n1e7_unit_laplacian_apply", "n": g.n, "nnz": g.nnz,
+           "launches": rows, "traffic_k1_f32": load_spmv_traffic()}
+    log("spmv: " + json.dumps(res))
+    return res
+
+
+def load_spmv_traffic():
+    """Counter bytes per launch of the k = 1 FP32 apply on the 10^7-node
+    graph, from the committed profile, if taken on the current source."""
+    import hashlib
+    p = os.path.join(ROOT, "profiles", "k_spmm_f32_configmodel1e7_k1_traffic.md")
+    if not os.path.exists(p):
+        return None
+    fields = {}
+    for line in open(p):
+        if ":" in line and not line.startswith(("#", " ", "|")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for src in ("paper_2310_11222_amd/csrc/spmm.hip", "paper_2310_11222_amd/csrc/device_common.hpp",
+                "paper_2310_11222_amd/csrc/nvd_internal.hpp"):
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if fields.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(w, pairs):
     """The oracle (FP64 Jacobi-PCG route, unmodified defaults) on `pairs`
     pairs of the same workload, single-threaded."""
@@ -202,6 +274,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-pairwise", action="store_true")
     ap.add_argument("--no-density", action="store_true")
+    ap.add_argument("--no-spmv", action="store_true",
+                    help="skip the reference SpMV loads on the 1e7-node graph")
+    ap.add_argument("--spmv-only", action="store_true",
+                    help="run only the reference SpMV loads (for profiling) and print them")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 512 MiB device copy first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -216,6 +292,9 @@ def main():
     from nvdgen import workload
 
     torch.cuda.set_device(0)
+    if args.spmv_only:
+        print(json.dumps(bench_spmv(args.calib_copy)), flush=True)
+        return
     if args.calib_copy:
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
@@ -358,6 +437,11 @@ def main():
         torch.cuda.empty_cache()
         batched = bench_batched(max(2, args.steps // 2), 1)
 
+    spmv = None
+    if not args.no_spmv:
+        torch.cuda.empty_cache()
+        spmv = bench_spmv()
+
     out = {
         "metric": "NVD distances/sec at rel err <=1e-6 vs FP64 oracle; SpMV HBM GB/s % of peak",
         "value": round(value, 2),
@@ -383,6 +467,7 @@ def main():
         "batched": batched,
         "all_pairs": all_pairs,
         "density_sweep": density,
+        "spmv_reference": spmv,
         "iters_mean": float(np.mean(iters_mixed)),
         "refine_mean": float(np.mean(refine)),
         "setup_s": round(setup_s, 3),
