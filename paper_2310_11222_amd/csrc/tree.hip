@@ -32,7 +32,16 @@
 
 namespace nvd {
 
-constexpr int kScanChunk = 2048;   // tour rows per scan block
+// Tour rows per scan block: 2048 on large forests, down to 256 on small
+// ones so that a short tour still spreads over many blocks (each lane walks
+// chunk / (256 / T) rows in sequence).
+constexpr int kScanChunkMax = 2048;
+constexpr int kScanChunkMin = 256;
+static int scan_chunk(long rows) {
+  int c = kScanChunkMin;
+  while (c < kScanChunkMax && (long)c * 1024 < rows) c <<= 1;
+  return c;
+}
 
 // ---------------------------------------------------------------------------
 // host: spanning forest and Euler tour
@@ -162,7 +171,7 @@ nvd_status ensure_tree(DevGraph* g, int T) {
     if (p) (void)hipFree(p);
   tp->E = tp->S = tp->part = nullptr;
   const size_t rows = 2 * (size_t)g->n;
-  const size_t nchunk = (rows + kScanChunk - 1) / kScanChunk;
+  const size_t nchunk = (rows + kScanChunkMin - 1) / kScanChunkMin;   // the most any chunk size needs
   NVD_HIP(hipMalloc((void**)&tp->E, sizeof(double) * rows * T));
   NVD_HIP(hipMalloc((void**)&tp->S, sizeof(double) * rows * T));
   NVD_HIP(hipMalloc((void**)&tp->part, sizeof(double) * nchunk * T));
@@ -223,24 +232,25 @@ __global__ void k_tour_get(int n, int T, const double* __restrict__ S, const int
 // lanes) owns a contiguous segment.  Phase 1: chunk sums; phase 2: exclusive
 // scan of the chunk sums per column; phase 3: segment prefixes plus the
 // chunk offset.  The split is the same in phases 1 and 3.
-__device__ __forceinline__ void seg_of(int T, long rows, int b, long* lo, long* hi, int* c) {
+__device__ __forceinline__ void seg_of(int T, long rows, int chunk, int b, long* lo, long* hi, int* c) {
   const int t = threadIdx.x;
   const int NJ = 256 / T;
   const int j = t / T;
   *c = t % T;
-  const long seg = (kScanChunk + NJ - 1) / NJ;
-  const long base = (long)b * kScanChunk;
-  const long end = min(rows, base + kScanChunk);
+  const long seg = (chunk + NJ - 1) / NJ;
+  const long base = (long)b * chunk;
+  const long end = min(rows, base + chunk);
   *lo = min(end, base + j * seg);
   *hi = min(end, *lo + seg);
 }
 
-__global__ __launch_bounds__(256) void k_scan_sums(long rows, int T, const double* __restrict__ E,
+__global__ __launch_bounds__(256) void k_scan_sums(long rows, int T, int chunk,
+                                                   const double* __restrict__ E,
                                                    double* __restrict__ part) {
   __shared__ double sh[256];
   long lo, hi;
   int c;
-  seg_of(T, rows, blockIdx.x, &lo, &hi, &c);
+  seg_of(T, rows, chunk, blockIdx.x, &lo, &hi, &c);
   double s = 0.0;
   for (long i = lo; i < hi; ++i) s += E[i * T + c];
   sh[threadIdx.x] = s;
@@ -280,13 +290,14 @@ __global__ __launch_bounds__(256) void k_scan_offsets(int nchunk, int T, double*
   }
 }
 
-__global__ __launch_bounds__(256) void k_scan_apply(long rows, int T, const double* __restrict__ E,
+__global__ __launch_bounds__(256) void k_scan_apply(long rows, int T, int chunk,
+                                                    const double* __restrict__ E,
                                                     const double* __restrict__ part,
                                                     double* __restrict__ S) {
   __shared__ double sh[256];
   long lo, hi;
   int c;
-  seg_of(T, rows, blockIdx.x, &lo, &hi, &c);
+  seg_of(T, rows, chunk, blockIdx.x, &lo, &hi, &c);
   double s = 0.0;
   for (long i = lo; i < hi; ++i) s += E[i * T + c];
   sh[threadIdx.x] = s;
@@ -301,10 +312,11 @@ __global__ __launch_bounds__(256) void k_scan_apply(long rows, int T, const doub
 }
 
 static void scan_rows(long rows, int T, const double* E, double* part, double* S, hipStream_t s) {
-  const int nchunk = (int)((rows + kScanChunk - 1) / kScanChunk);
-  k_scan_sums<<<nchunk, 256, 0, s>>>(rows, T, E, part);
+  const int chunk = scan_chunk(rows);
+  const int nchunk = (int)((rows + chunk - 1) / chunk);
+  k_scan_sums<<<nchunk, 256, 0, s>>>(rows, T, chunk, E, part);
   k_scan_offsets<<<T, 256, 0, s>>>(nchunk, T, part);
-  k_scan_apply<<<nchunk, 256, 0, s>>>(rows, T, E, part, S);
+  k_scan_apply<<<nchunk, 256, 0, s>>>(rows, T, chunk, E, part, S);
 }
 
 template <typename V>
