@@ -152,6 +152,35 @@ def test_tree_degenerate_graphs(n, edges):
         assert all(i["status"] == 0 for i in info)
 
 
+@pytest.mark.parametrize("precision,rtol,tol", PREC)
+def test_tree_warm_start(precision, rtol, tol):
+    """Warm start with the tree preconditioner: the residual of the caller's
+    x0 is taken, then the tree-preconditioned CG restarts from it.  From the
+    exact solution plus noise on a weighted forest with a cycle the result
+    matches the dense oracle; from the solution itself nothing is left to do."""
+    import torch
+    rng = np.random.default_rng(21)
+    t = random_tree(3000, rng, rng.uniform(0.5, 2.0, 2999))
+    eu = np.concatenate([t.eu, [5]])
+    ev = np.concatenate([t.ev, [2500]])
+    ew = np.concatenate([t.ew, [1.3]])
+    g = Graph(t.n, np.minimum(eu, ev), np.maximum(eu, ev), ew)
+    P = rng.random((g.n, 4))
+    Q = np.where(rng.random((g.n, 4)) < 0.2, rng.random((g.n, 4)), 0.0)
+    say("tree warm start", precision)
+    dg = dev_graph(g)
+    ref = oracle.ge_dense(g.n, g.row_ptr, g.col_idx, g.w, P, Q)["d"]
+    d0, X, _ = dg.distances(P, Q, precision="fp64", rtol=1e-12, precond="tree", return_x=True)
+    X0 = X + 1e-3 * torch.as_tensor(rng.standard_normal(X.shape), device=X.device)
+    d, _, info = dg.distances(P, Q, precision=precision, rtol=rtol, precond="tree", X0=X0)
+    assert rel_err(d.cpu().numpy(), ref).max() <= tol
+    assert all(i["status"] == 0 for i in info)
+    assert max(i["iters"] for i in info) <= 12, info[0]
+    d2, _, info2 = dg.distances(P, Q, precision=precision, rtol=rtol, precond="tree", X0=X.clone())
+    assert rel_err(d2.cpu().numpy(), ref).max() <= tol
+    assert all(i["status"] == 0 for i in info2)
+
+
 def test_pairwise_with_tree_preconditioner():
     g, P, _ = density_graph("ws", 2)
     V = P[:, :6]
