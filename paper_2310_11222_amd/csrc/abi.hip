@@ -341,6 +341,16 @@ nvd_status nvd_graph_set_weights(nvd_graph* h, const double* w, void* stream) {
     return NVD_E_DEVICE;
   }
   g->weighted = true;
+  // the spanning forest (tree preconditioner) holds 1/w of its edges and is
+  // built from the host copy of the weights: refresh the copy, drop the forest
+  free_tree(g->tree);
+  g->tree = nullptr;
+  g->h_w.resize(std::max(g->nnz, 1));
+  if (hipMemcpy(g->h_w.data(), g->w64, sizeof(double) * g->nnz, hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("nvd_graph_set_weights: copying the weights back failed");
+    return NVD_E_DEVICE;
+  }
+  g->h_w.resize(g->nnz);
   if (hflag) {
     set_error(std::string("nvd_graph_set_weights: ") +
               ((hflag & 1) ? "a weight is not a finite positive number" : "") +

@@ -181,6 +181,31 @@ def test_tree_warm_start(precision, rtol, tol):
     assert all(i["status"] == 0 for i in info2)
 
 
+def test_tree_follows_new_weights():
+    """The forest holds 1/w of its edges: after nvd_graph_set_weights it is
+    rebuilt from the new weights (a tree stays one FP64 iteration), and the
+    distances follow them."""
+    import torch
+    rng = np.random.default_rng(31)
+    t = random_tree(5000, rng)                              # created unweighted
+    P = rng.random((t.n, 4))
+    Q = rng.random((t.n, 4))
+    say("tree new weights")
+    dg = dev_graph(t)
+    d0, _, info0 = dg.distances(P, Q, precision="fp64", rtol=1e-10, precond="tree")
+    assert max(i["iters"] for i in info0) <= 2
+    ew = rng.uniform(0.2, 5.0, t.num_edges)
+    tw = t.with_weights(ew)
+    dg.set_weights(torch.as_tensor(tw.w))                   # CSR order, both directions
+    ref = oracle.ge_tree(tw.n, tw.row_ptr, tw.col_idx, tw.w, P, Q)["d"]
+    for precision, rtol, tol in PREC:
+        d, _, info = dg.distances(P, Q, precision=precision, rtol=rtol, precond="tree")
+        assert rel_err(d.cpu().numpy(), ref).max() <= tol, precision
+        assert all(i["status"] == 0 for i in info)
+        if precision == "fp64":
+            assert max(i["iters"] for i in info) <= 2, info[0]
+
+
 def test_pairwise_with_tree_preconditioner():
     g, P, _ = density_graph("ws", 2)
     V = P[:, :6]
