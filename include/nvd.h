@@ -238,7 +238,8 @@ nvd_status nvd_tune_query(nvd_graph* g, int32_t k, int32_t precision,
  * its mirror entry's (NVD_E_GRAPH otherwise; the graph then holds the
  * rejected values and must not be used until valid weights are set).
  * Synchronous with respect to `stream`.  Batches made earlier keep their
- * own copy. */
+ * own copy; a spanning forest built for the tree preconditioner is dropped
+ * and rebuilt from the new weights when next needed. */
 nvd_status nvd_graph_set_weights(nvd_graph* g, const double* w, void* stream);
 
 /* ---- adjoint of d^2 with respect to the edge weights ---------------------
