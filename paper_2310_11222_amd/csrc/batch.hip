@@ -561,21 +561,18 @@ __device__ __noinline__ void solve_graph(const BatchArgs& a, int gi, Team& tm, c
 #pragma unroll
           for (int v = 0; v < N; ++v) al[v] = (V)L.alpha[(t * N + v) % T];
           const long i1 = (long)hi * T / N;
-          const VT* __restrict__ P4 = reinterpret_cast<const VT*>(pv);
+          // (c += alpha p is left to the direction phase, which reads p anyway)
           const VT* __restrict__ Q4 = reinterpret_cast<const VT*>(qv);
           VT* __restrict__ R4 = reinterpret_cast<VT*>(rv);
-          VT* __restrict__ C4 = reinterpret_cast<VT*>(cv);
           for (long i0 = t; i0 < i1; i0 += (long)U * BBS) {
-            VT pvv[U], qvv[U], rvv[U], cvv[U];
+            VT qvv[U], rvv[U];
             V iv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
               const long i = i0 + (long)u * BBS;
               if (i < i1) {
-                pvv[u] = P4[i];
                 qvv[u] = Q4[i];
                 rvv[u] = R4[i];
-                cvv[u] = C4[i];
                 iv[u] = invd[(i * N) / T];     // T >= N: one row per vector
               }
             }
@@ -583,19 +580,15 @@ __device__ __noinline__ void solve_graph(const BatchArgs& a, int gi, Team& tm, c
             for (int u = 0; u < U; ++u) {
               const long i = i0 + (long)u * BBS;
               if (i < i1) {
-                V* ps = reinterpret_cast<V*>(&pvv[u]);
                 V* qs = reinterpret_cast<V*>(&qvv[u]);
                 V* rs = reinterpret_cast<V*>(&rvv[u]);
-                V* cs = reinterpret_cast<V*>(&cvv[u]);
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
-                  cs[v] += al[v] * ps[v];
                   rs[v] -= al[v] * qs[v];
                   const double rd = (double)rs[v];
                   acc[0][v] += rd * rd * (double)iv[u];
                   acc[1][v] += rd * rd;
                 }
-                C4[i] = cvv[u];
                 R4[i] = rvv[u];
               }
             }
@@ -604,9 +597,7 @@ __device__ __noinline__ void solve_graph(const BatchArgs& a, int gi, Team& tm, c
           const V al = (V)L.alpha[c];
           for (long e = e0; e < e1; e += STEP) {
             const long i = e / T;
-            const V pe = vld<SH>(&pv[e]);
             const V re = rv[e] - al * qv[e];
-            cv[e] = cv[e] + al * pe;
             rv[e] = re;
             const double rd = (double)re;
             acc[0][0] += rd * rd * (double)invd[i];
@@ -654,14 +645,18 @@ __device__ __noinline__ void solve_graph(const BatchArgs& a, int gi, Team& tm, c
         if constexpr (S::VEC) {
           using VT = typename Vec16<V>::type;
           constexpr int U = 2;
-          V be[N];
+          V al[N], be[N];
 #pragma unroll
-          for (int v = 0; v < N; ++v) be[v] = (V)L.beta[(t * N + v) % T];
+          for (int v = 0; v < N; ++v) {
+            al[v] = (V)L.alpha[(t * N + v) % T];
+            be[v] = (V)L.beta[(t * N + v) % T];
+          }
           const long i1 = (long)hi * T / N;
           VT* __restrict__ P4 = reinterpret_cast<VT*>(pv);
+          VT* __restrict__ C4 = reinterpret_cast<VT*>(cv);
           const VT* __restrict__ R4 = reinterpret_cast<const VT*>(rv);
           for (long i0 = t; i0 < i1; i0 += (long)U * BBS) {
-            VT pvv[U], rvv[U];
+            VT pvv[U], rvv[U], cvv[U];
             V iv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -669,6 +664,7 @@ __device__ __noinline__ void solve_graph(const BatchArgs& a, int gi, Team& tm, c
               if (i < i1) {
                 pvv[u] = P4[i];
                 rvv[u] = R4[i];
+                cvv[u] = C4[i];
                 iv[u] = invd[(i * N) / T];
               }
             }
@@ -677,18 +673,26 @@ __device__ __noinline__ void solve_graph(const BatchArgs& a, int gi, Team& tm, c
               const long i = i0 + (long)u * BBS;
               if (i < i1) {
                 V* ps = reinterpret_cast<V*>(&pvv[u]);
+                V* cs = reinterpret_cast<V*>(&cvv[u]);
                 const V* rs = reinterpret_cast<const V*>(&rvv[u]);
 #pragma unroll
-                for (int v = 0; v < N; ++v) ps[v] = rs[v] * iv[u] + be[v] * ps[v];
+                for (int v = 0; v < N; ++v) {
+                  cs[v] += al[v] * ps[v];      // this iteration's step, old p
+                  ps[v] = rs[v] * iv[u] + be[v] * ps[v];
+                }
+                C4[i] = cvv[u];
                 P4[i] = pvv[u];
               }
             }
           }
         } else {
+          const V al = (V)L.alpha[c];
           const V be = (V)L.beta[c];
           for (long e = e0; e < e1; e += STEP) {
             const long i = e / T;
-            vst<SH>(&pv[e], rv[e] * invd[i] + be * vld<SH>(&pv[e]));
+            const V pe = vld<SH>(&pv[e]);
+            cv[e] = cv[e] + al * pe;
+            vst<SH>(&pv[e], rv[e] * invd[i] + be * pe);
           }
         }
         team_sync(tm);
