@@ -173,6 +173,40 @@ def bench_density():
     return {"workload": "density_sweep_n1e4_deg1_to_64", "models": out}
 
 
+def bench_tree_large():
+    """A 10^6-node tree-like graph (Barabasi-Albert with one link per new
+    node: a tree), 16 pairs on 5% supports, mixed precision to 1e-8: the
+    Jacobi diagonal against the spanning-forest preconditioner (the time of
+    one call after a warm-up call, which also builds the forest)."""
+    import numpy as np
+    import torch
+    import paper_2310_11222_amd as nvd
+    from nvdgen import barabasi_albert, sparse_support_pairs
+    rng = np.random.default_rng(np.random.SeedSequence([2310, 11222, 77]))
+    g = barabasi_albert(1_000_000, 1, rng)
+    P, Q = sparse_support_pairs(g.n, 16, 0.05, rng)
+    dg = nvd.Graph(g.row_ptr, g.col_idx, None)
+    Pd = torch.as_tensor(P).cuda()
+    Qd = torch.as_tensor(Q).cuda()
+    res = {"workload": "ba_tree_n1e6_m1_k16", "n": g.n, "nnz": g.nnz, "pairs": 16}
+    ds = {}
+    for pre in ("jacobi", "tree"):
+        dg.distances(Pd, Qd, precision="mixed", rtol=1e-8, precond=pre)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d, _, info = dg.distances(Pd, Qd, precision="mixed", rtol=1e-8, precond=pre)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ds[pre] = d.cpu().numpy()
+        res[pre] = {"ms_per_call": round(t * 1e3, 3), "distances_per_s": round(16 / t, 1),
+                    "iters": max(i["iters"] for i in info),
+                    "converged": all(i["status"] == 0 for i in info)}
+    res["max_rel_diff_tree_vs_jacobi"] = float(np.max(np.abs(ds["tree"] - ds["jacobi"]) / ds["jacobi"]))
+    dg.close()
+    log("tree-like graph: " + json.dumps(res))
+    return res
+
+
 def bench_spmv(calib_copy=False):
     """The reference SpMV loads for the HBM claim: Y = L X on the 10^7-node
     power-law configuration-model graph (unit weights), k = 1 and 16 columns,
@@ -273,7 +307,8 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-5)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-pairwise", action="store_true")
-    ap.add_argument("--no-density", action="store_true")
+    ap.add_argument("--no-density", action="store_true",
+                    help="skip the density sweep and the 1e6-node tree-like graph")
     ap.add_argument("--no-spmv", action="store_true",
                     help="skip the reference SpMV loads on the 1e7-node graph")
     ap.add_argument("--spmv-only", action="store_true",
@@ -430,6 +465,7 @@ def main():
         log(f"all pairs: {all_pairs}")
 
     density = None if args.no_density else bench_density()
+    tree_large = None if args.no_density else bench_tree_large()
 
     batched = None
     if not args.no_batched:
@@ -467,6 +503,7 @@ def main():
         "batched": batched,
         "all_pairs": all_pairs,
         "density_sweep": density,
+        "tree_like_1e6": tree_large,
         "spmv_reference": spmv,
         "iters_mean": float(np.mean(iters_mixed)),
         "refine_mean": float(np.mean(refine)),
