@@ -244,6 +244,23 @@ __device__ __forceinline__ void seg_of(int T, long rows, int chunk, int b, long*
   *hi = min(end, *lo + seg);
 }
 
+// Sum of E[i][c] over i in [lo, hi), loads issued 8 rows at a time (one
+// load in flight per lane left the scans latency-bound), added in row order.
+__device__ __forceinline__ double seg_sum(const double* __restrict__ E, long lo, long hi, int T, int c) {
+  constexpr int B = 8;
+  double s = 0.0;
+  long i = lo;
+  for (; i + B <= hi; i += B) {
+    double e[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) e[k] = E[(i + k) * T + c];
+#pragma unroll
+    for (int k = 0; k < B; ++k) s += e[k];
+  }
+  for (; i < hi; ++i) s += E[i * T + c];
+  return s;
+}
+
 __global__ __launch_bounds__(256) void k_scan_sums(long rows, int T, int chunk,
                                                    const double* __restrict__ E,
                                                    double* __restrict__ part) {
@@ -251,9 +268,7 @@ __global__ __launch_bounds__(256) void k_scan_sums(long rows, int T, int chunk,
   long lo, hi;
   int c;
   seg_of(T, rows, chunk, blockIdx.x, &lo, &hi, &c);
-  double s = 0.0;
-  for (long i = lo; i < hi; ++i) s += E[i * T + c];
-  sh[threadIdx.x] = s;
+  sh[threadIdx.x] = seg_sum(E, lo, hi, T, c);
   __syncthreads();
   if ((int)threadIdx.x < T) {
     double tot = 0.0;
@@ -298,14 +313,24 @@ __global__ __launch_bounds__(256) void k_scan_apply(long rows, int T, int chunk,
   long lo, hi;
   int c;
   seg_of(T, rows, chunk, blockIdx.x, &lo, &hi, &c);
-  double s = 0.0;
-  for (long i = lo; i < hi; ++i) s += E[i * T + c];
-  sh[threadIdx.x] = s;
+  sh[threadIdx.x] = seg_sum(E, lo, hi, T, c);
   __syncthreads();
   const int j = threadIdx.x / T;
   double run = part[(long)blockIdx.x * T + c];
   for (int q = 0; q < j; ++q) run += sh[q * T + c];
-  for (long i = lo; i < hi; ++i) {
+  constexpr int B = 8;
+  long i = lo;
+  for (; i + B <= hi; i += B) {
+    double e[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) e[k] = E[(i + k) * T + c];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      run += e[k];
+      S[(i + k) * T + c] = run;
+    }
+  }
+  for (; i < hi; ++i) {
     run += E[i * T + c];
     S[i * T + c] = run;
   }
