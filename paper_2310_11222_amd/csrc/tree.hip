@@ -15,8 +15,8 @@
 //   x_v = S2[tin_v],  S2 = prefix of (+f_v/w_v at tin_v, -f_v/w_v at tout_v)
 // so one solve is two scans over 2n x T values, O(n) work in O(log n)
 // depth whatever the depth of the tree.  The scans run in FP64 (prefix sums
-// cancel) with a fixed chunk and segment split, so results repeat bit for
-// bit.
+// cancel) with a chunk and segment split that depend only on the tour
+// length and the tile, so results repeat bit for bit.
 //
 // Subtracting mu_c makes the map the pseudoinverse on r's component means
 // too (constants go to zero).  Without it the solve would be the grounded
