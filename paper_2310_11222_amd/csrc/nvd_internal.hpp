@@ -98,6 +98,7 @@ struct TreePre {
   double* winv = nullptr;      // [n] 1 / weight of the edge to the parent (0 at roots)
   int* rbeg = nullptr;         // [n] tin of v's root: v's component is the tour
   int* rend = nullptr;         // [n] range [rbeg, rend] (tout of the root)
+  int* tnode = nullptr;        // [2n] node entered at each tour position, -1 where one is left
   double* E = nullptr;         // [2n][cap_tile] tour values
   double* S = nullptr;         // [2n][cap_tile] their prefix sums
   double* part = nullptr;      // [chunks][cap_tile] scan offsets

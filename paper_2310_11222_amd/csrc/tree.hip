@@ -16,7 +16,9 @@
 // so one solve is two scans over 2n x T values, O(n) work in O(log n)
 // depth whatever the depth of the tree.  The scans run in FP64 (prefix sums
 // cancel) with a chunk and segment split that depend only on the tour
-// length and the tile, so results repeat bit for bit.
+// length and the tile, so results repeat bit for bit.  The second scan
+// writes x_v from its running sum at tin_v (tnode: the node entered at each
+// tour position) instead of storing S2 for a separate gather.
 //
 // Subtracting mu_c makes the map the pseudoinverse on r's component means
 // too (constants go to zero).  Without it the solve would be the grounded
@@ -108,11 +110,12 @@ static nvd_status build_tree(DevGraph* g) {
     }
   }
   std::vector<double> winv(n);
-  std::vector<int> rbeg(n), rend(n);
+  std::vector<int> rbeg(n), rend(n), tnode(2 * (size_t)n, -1);
   for (int v = 0; v < n; ++v) {
     winv[v] = parent[v] >= 0 ? 1.0 / pw[v] : 0.0;
     rbeg[v] = tin[root_of[v]];
     rend[v] = tout[root_of[v]];
+    tnode[tin[v]] = v;
   }
   TreePre* tp = new TreePre();
   tp->n_tree_edges = tree_edges;
@@ -128,11 +131,13 @@ static nvd_status build_tree(DevGraph* g) {
   al((void**)&tp->winv, sizeof(double) * n);
   al((void**)&tp->rbeg, sizeof(int) * n);
   al((void**)&tp->rend, sizeof(int) * n);
+  al((void**)&tp->tnode, sizeof(int) * 2 * (size_t)n);
   if (st == NVD_OK &&
       (hipMemcpy(tp->tin, tin.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess ||
        hipMemcpy(tp->tout, tout.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess ||
        hipMemcpy(tp->rbeg, rbeg.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess ||
        hipMemcpy(tp->rend, rend.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(tp->tnode, tnode.data(), sizeof(int) * 2 * (size_t)n, hipMemcpyHostToDevice) != hipSuccess ||
        hipMemcpy(tp->winv, winv.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess)) {
     set_error("tree preconditioner: upload failed");
     st = NVD_E_DEVICE;
@@ -147,7 +152,7 @@ static nvd_status build_tree(DevGraph* g) {
 
 void free_tree(TreePre* tp) {
   if (!tp) return;
-  void* ptrs[] = {tp->tin, tp->tout, tp->winv, tp->rbeg, tp->rend, tp->E, tp->S, tp->part};
+  void* ptrs[] = {tp->tin, tp->tout, tp->winv, tp->rbeg, tp->rend, tp->tnode, tp->E, tp->S, tp->part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete tp;
@@ -216,15 +221,6 @@ __global__ void k_tour_flow(int n, int T, const V* __restrict__ r, const int* __
     E[a] = y;
     E[b] = -y;
   }
-}
-
-// z_v = S[tin_v]
-template <typename V>
-__global__ void k_tour_get(int n, int T, const double* __restrict__ S, const int* __restrict__ tin,
-                           V* __restrict__ z) {
-  const long tot = (long)n * T;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x)
-    z[e] = (V)S[(long)tin[e / T] * T + e % T];
 }
 
 // Scan of a rows x T row-major array along the rows, per column.  Block b
@@ -305,10 +301,15 @@ __global__ __launch_bounds__(256) void k_scan_offsets(int nchunk, int T, double*
   }
 }
 
+// TO_Z: instead of S, write the running sum at the position where node v is
+// entered to z_v (the second scan, whose prefix is only read there).
+template <typename V, bool TO_Z>
 __global__ __launch_bounds__(256) void k_scan_apply(long rows, int T, int chunk,
                                                     const double* __restrict__ E,
                                                     const double* __restrict__ part,
-                                                    double* __restrict__ S) {
+                                                    double* __restrict__ S,
+                                                    const int* __restrict__ tnode,
+                                                    V* __restrict__ z) {
   __shared__ double sh[256];
   long lo, hi;
   int c;
@@ -322,26 +323,41 @@ __global__ __launch_bounds__(256) void k_scan_apply(long rows, int T, int chunk,
   long i = lo;
   for (; i + B <= hi; i += B) {
     double e[B];
+    int tv[B];
 #pragma unroll
-    for (int k = 0; k < B; ++k) e[k] = E[(i + k) * T + c];
+    for (int k = 0; k < B; ++k) {
+      e[k] = E[(i + k) * T + c];
+      if constexpr (TO_Z) tv[k] = tnode[i + k];
+    }
 #pragma unroll
     for (int k = 0; k < B; ++k) {
       run += e[k];
-      S[(i + k) * T + c] = run;
+      if constexpr (TO_Z) {
+        if (tv[k] >= 0) z[(long)tv[k] * T + c] = (V)run;
+      } else {
+        S[(i + k) * T + c] = run;
+      }
     }
   }
   for (; i < hi; ++i) {
     run += E[i * T + c];
-    S[i * T + c] = run;
+    if constexpr (TO_Z) {
+      const int v = tnode[i];
+      if (v >= 0) z[(long)v * T + c] = (V)run;
+    } else {
+      S[i * T + c] = run;
+    }
   }
 }
 
-static void scan_rows(long rows, int T, const double* E, double* part, double* S, hipStream_t s) {
+template <typename V, bool TO_Z>
+static void scan_rows(long rows, int T, const double* E, double* part, double* S, const int* tnode,
+                      V* z, hipStream_t s) {
   const int chunk = scan_chunk(rows);
   const int nchunk = (int)((rows + chunk - 1) / chunk);
   k_scan_sums<<<nchunk, 256, 0, s>>>(rows, T, chunk, E, part);
   k_scan_offsets<<<T, 256, 0, s>>>(nchunk, T, part);
-  k_scan_apply<<<nchunk, 256, 0, s>>>(rows, T, chunk, E, part, S);
+  k_scan_apply<V, TO_Z><<<nchunk, 256, 0, s>>>(rows, T, chunk, E, part, S, tnode, z);
 }
 
 template <typename V>
@@ -351,11 +367,10 @@ static nvd_status tree_solve_t(DevGraph* g, int T, const V* r, V* z, hipStream_t
   const long rows = 2L * n;
   const int grid = (int)std::min<long>(4096, ((long)n * T + 255) / 256);
   k_tour_put<V><<<std::max(grid, 1), 256, 0, s>>>(n, T, r, tp->tin, tp->tout, tp->E);
-  scan_rows(rows, T, tp->E, tp->part, tp->S, s);
+  scan_rows<V, false>(rows, T, tp->E, tp->part, tp->S, nullptr, (V*)nullptr, s);
   k_tour_flow<V><<<std::max(grid, 1), 256, 0, s>>>(n, T, r, tp->tin, tp->tout, tp->rbeg, tp->rend,
                                                    tp->winv, tp->S, tp->E);
-  scan_rows(rows, T, tp->E, tp->part, tp->S, s);
-  k_tour_get<V><<<std::max(grid, 1), 256, 0, s>>>(n, T, tp->S, tp->tin, z);
+  scan_rows<V, true>(rows, T, tp->E, tp->part, nullptr, tp->tnode, z, s);
   NVD_HIP(hipGetLastError());
   return NVD_OK;
 }
