@@ -81,7 +81,7 @@ static void batch_drop_graph(nvd_batch* b) {
   b->key.clear();
 }
 
-static void batch_free(nvd_batch* b) {
+static inline void batch_free(nvd_batch* b) {
   batch_drop_graph(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   void* ptrs[] = {b->rp, b->ci, b->w64, b->w32, b->invd64, b->invd32,
