@@ -25,7 +25,8 @@
  *   - an isolated node is its own component and contributes nothing;
  *   - delta_bar = 0 gives d = 0 exactly, with no iterations.
  *
- * Layouts.  A graph is a symmetric CSR on the host: row_ptr int64 [n+1],
+ * Layouts.  A graph is a symmetric CSR (host arrays, or device arrays with
+ * nvd_graph_create_ex and NVD_PTR_DEVICE): row_ptr int64 [n+1],
  * col_idx int32 [nnz] (both directions of every edge present, equal weights,
  * no repeated (i, j) within a row), weights float64 [nnz] or NULL for unit
  * weights.  Node-vector blocks are row-major n x k float64 with a leading
@@ -38,9 +39,15 @@
  * thread-safe: one call in flight per handle.
  *
  * Streams.  Every `stream` argument is a hipStream_t passed as void*
- * (NULL = the default stream).  Solve calls enqueue their work on that stream
- * and return after it has completed (they poll convergence flags on the
- * host), so outputs are ready on return.
+ * (NULL = the default stream).  Solve calls (nvd_distances, nvd_pairwise,
+ * nvd_batch_distances, nvd_graph_set_weights) enqueue their work on that
+ * stream and return after it has completed, so outputs are ready on return:
+ * the iteration count is data dependent, and the host reads a few words of
+ * convergence state (a 24-byte copy and a stream synchronisation, ~10-20 us)
+ * after each chunk of CG iterations.  The chunk is sized from the observed
+ * decay of the worst residual, so a solve of I iterations polls about
+ * 3 + I / 8 times.  nvd_laplacian_apply, nvd_project and the adjoint calls
+ * only enqueue.
  *
  * Errors.  Every call returns an nvd_status.  Argument and graph errors are
  * found before anything is enqueued; nvd_last_error() then holds a message
@@ -85,17 +92,22 @@ enum {
                                launch instead of the sweep solver */
   NVD_PRECOND_TREE = 4u,    /* nvd_distances / nvd_pairwise: precondition CG
                                with a spanning forest of the graph (exact
-                               tree solve, section 3.2 tree preconditioners)
+                               tree solve; a tree-based solver is one of the
+                               solvers compared in Table 1, "Aug Tree")
                                instead of the Jacobi diagonal; for very sparse
                                graphs.  Not for batches. */
-  NVD_PRECOND_AUTO = 8u     /* nvd_distances / nvd_pairwise: the spanning
+  NVD_PRECOND_AUTO = 8u,    /* nvd_distances / nvd_pairwise: the spanning
                                forest when at most n/100 edges lie off it
                                (m - n + c <= n / 100 for m edges and c
                                components: tree PCG then needs at most that
                                many iterations plus one in exact arithmetic),
                                else the Jacobi diagonal.  Batches always use
                                the Jacobi diagonal under this flag. */
+  NVD_OUT_DSQ = 16u         /* nvd_distances: d_out receives d^2 (the
+                               quadratic form, clamped at 0) instead of d */
 };
+/* nvd_graph_create_ex flags: where the CSR arrays live */
+enum { NVD_PTR_HOST = 0u, NVD_PTR_DEVICE = 1u };
 
 typedef struct nvd_graph nvd_graph;
 typedef struct nvd_batch nvd_batch;
@@ -115,11 +127,12 @@ typedef struct nvd_opts {
   int32_t tile_k;      /* columns per SpMM pass: 1,2,4,8,16,32,64; 0 = the
                           library's autotuned choice */
   uint32_t flags;      /* NVD_WARM_START, NVD_BATCH_PERSISTENT, NVD_PRECOND_TREE,
-                          NVD_PRECOND_AUTO */
+                          NVD_PRECOND_AUTO, NVD_OUT_DSQ */
 } nvd_opts;
 
 typedef struct nvd_pair_info {
-  int32_t status;       /* NVD_OK, NVD_E_NOCONV or NVD_E_BREAKDOWN */
+  int32_t status;       /* NVD_OK, NVD_E_NOCONV or NVD_E_BREAKDOWN
+                           (NVD_E_DEVICE: the persistent batch launch failed) */
   int32_t iters;        /* CG iterations (all inner solves summed) */
   int32_t refine_steps; /* MIXED outer steps (0 for FP64) */
   int32_t reserved;
@@ -158,6 +171,13 @@ nvd_status nvd_opts_default(nvd_opts* o);
 nvd_status nvd_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr,
                             const int32_t* col_idx, const double* weights,
                             void* stream, nvd_graph** out);
+/* As nvd_graph_create; flags NVD_PTR_DEVICE: row_ptr, col_idx and weights
+ * are device pointers (same layouts).  They are read after the work already
+ * on `stream` has completed and copied to the host, where validation runs;
+ * the caller keeps ownership.  Unknown flags: NVD_E_ARG. */
+nvd_status nvd_graph_create_ex(int64_t n, int64_t nnz, const int64_t* row_ptr,
+                               const int32_t* col_idx, const double* weights,
+                               uint32_t flags, void* stream, nvd_graph** out);
 nvd_status nvd_graph_destroy(nvd_graph* g);
 nvd_status nvd_graph_stats(const nvd_graph* g, nvd_stats* s);
 /* Host copies of the component label of every node (int32 [n], labels
@@ -234,9 +254,9 @@ nvd_status nvd_tune_query(nvd_graph* g, int32_t k, int32_t precision,
  * w: device float64 [nnz] in the order of the CSR given to nvd_graph_create
  * (self-loop entries ignored).  Replaces the weights (a graph created with
  * unit weights becomes weighted), recomputes degrees and their inverses, and
- * checks on the device that every value is finite and positive and equal to
- * its mirror entry's (NVD_E_GRAPH otherwise; the graph then holds the
- * rejected values and must not be used until valid weights are set).
+ * checks on the device, before anything is replaced, that every value is
+ * finite and positive and equal to its mirror entry's (NVD_E_GRAPH
+ * otherwise; the graph then keeps its previous weights).
  * Synchronous with respect to `stream`.  Batches made earlier keep their
  * own copy; a spanning forest built for the tree preconditioner is dropped
  * and rebuilt from the new weights when next needed. */
@@ -249,12 +269,31 @@ nvd_status nvd_graph_set_weights(nvd_graph* g, const double* w, void* stream);
  * nvd_graph_create (same order, self-loop entries get 0):
  *     grad_w[e] = -1/2 * sum_j gscale_j * (X[i, j] - X[c, j])^2,  c = col_idx[e],
  * so that the two stored directions of an edge sum to d(sum_j g_j d_j^2)/dw
- * of that undirected edge.  The gradients with respect to P and Q are
- * 2 X diag(gscale) and its negative (no kernel needed).  grad_w: device
- * float64 [nnz].  Asynchronous. */
+ * of that undirected edge (section 3.1's L is linear in w: dL/dw_e is the
+ * Laplacian of the single edge e, and d(delta^T L^+ delta)/dw_e =
+ * -(x_i - x_j)^2 with x = L^+ delta).  grad_w: device float64 [nnz].
+ * Asynchronous. */
 nvd_status nvd_grad_weights(nvd_graph* g, int32_t k, const double* X,
                             int64_t ldx, const double* gscale, double* grad_w,
                             void* stream);
+
+/* ---- adjoint of d^2 with respect to the node vectors ----------------------
+ * d(sum_j g_j d_j^2)/dP = 2 X diag(gscale) and d/dQ = -2 X diag(gscale),
+ * with X the saved solutions (x_j = L^+ delta_j; L^+ is symmetric, so no
+ * second solve).  X: device float64 n x k (ldx); gscale: device [k];
+ * GP, GQ: device float64 n x k (ldp, ldq), either may be NULL (not both).
+ * Asynchronous. */
+nvd_status nvd_grad_vectors(nvd_graph* g, int32_t k, const double* X,
+                            int64_t ldx, const double* gscale, double* GP,
+                            int64_t ldp, double* GQ, int64_t ldq, void* stream);
+
+/* ---- upstream gradient on d to the scale on d^2 ---------------------------
+ * gscale_j = g_d_j / (2 d_j) where d_j > 0, else 0 (d is not differentiable
+ * at 0; zero is the minimum-norm subgradient).  Feeds nvd_grad_vectors and
+ * nvd_grad_weights for gradients of d itself.  All device float64 [k].
+ * Asynchronous. */
+nvd_status nvd_grad_scale_from_d(int32_t k, const double* g_d, const double* d,
+                                 double* gscale, void* stream);
 
 /* ---- batches of graphs ----------------------------------------------------
  * nvd_batch_create packs G graphs into one device structure (the graphs may

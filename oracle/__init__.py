@@ -42,20 +42,5 @@ from .pairwise import pairwise_dense, pairwise_pcg
 
 __all__ = ["laplacian_dense", "laplacian_sparse", "components", "project",
            "ge_dense", "ge_grounded", "ge_pcg", "ge_tree", "ge_cycle",
-           "closed_forms", "grad_dense", "distance"]
+           "closed_forms", "grad_dense", "pairwise_dense", "pairwise_pcg"]
 
-
-def distance(n, row_ptr, col_idx, w, P, Q, method="auto", **kw):
-    """Dispatch to one route; returns (d, x) with d of shape (k,) and x the
-    per-component mean-zero solution L^+ (P - Q), shape (n, k)."""
-    if method == "auto":
-        method = "dense" if n <= 5000 else "pcg"
-    if method == "dense":
-        r = ge_dense(n, row_ptr, col_idx, w, P, Q)
-    elif method == "grounded":
-        r = ge_grounded(n, row_ptr, col_idx, w, P, Q)
-    elif method == "pcg":
-        r = ge_pcg(n, row_ptr, col_idx, w, P, Q, **kw)
-    else:
-        raise ValueError(method)
-    return r["d"], r["x"]

@@ -19,14 +19,7 @@ import numpy as np
 
 from .laplacian import laplacian_dense, components
 
-__all__ = ["ge_dense", "pinv_dense"]
-
-
-def pinv_dense(L, c):
-    """L^+ from eigh, dropping exactly the c smallest eigenpairs."""
-    lam, U = np.linalg.eigh(L)
-    Uk = U[:, c:]
-    return (Uk / lam[c:]) @ Uk.T, lam
+__all__ = ["ge_dense"]
 
 
 def ge_dense(n, row_ptr, col_idx, w, P, Q):

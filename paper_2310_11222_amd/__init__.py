@@ -11,7 +11,9 @@ if the library is missing, calls fail loudly.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -21,7 +23,7 @@ from ._abi import (NvdOpts, PairInfo, Stats, NvdError, check, load,
                    NVD_FP64, NVD_MIXED, NVD_DT_F64, NVD_DT_F32, NVD_WARM_START)
 
 __all__ = ["Graph", "Batch", "distance", "opts", "load", "NvdError", "PairInfo",
-           "NVD_FP64", "NVD_MIXED"]
+           "NVD_FP64", "NVD_MIXED", "grad_scale_from_d"]
 
 
 def _torch():
@@ -44,9 +46,50 @@ def _as_dev64(M, name):
         M = torch.as_tensor(np.asarray(M, dtype=np.float64))
     if M.dim() == 1:
         M = M.reshape(-1, 1)
-    if M.dtype != torch.float64 or not M.is_cuda or M.stride(1) != 1:
+    if M.dim() != 2:
+        raise ValueError(f"{name} must be a vector or a 2-D block, got shape {tuple(M.shape)}")
+    if M.dtype != torch.float64 or not M.is_cuda or M.stride(1) != 1 or M.stride(0) < M.shape[1]:
         M = M.to(device="cuda", dtype=torch.float64).contiguous()
     return M
+
+
+def _check_out(t, name, shape, dtype):
+    """A caller-supplied output buffer: a CUDA tensor of the given shape and
+    dtype whose rows are contiguous (the library writes through its data
+    pointer with row stride t.stride(0))."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.dim() == 2 and (t.stride(1) != 1 or t.stride(0) < t.shape[1]):
+        raise ValueError(f"{name} must have unit column stride and rows that do not overlap")
+    if t.dim() == 1 and t.stride(0) != 1:
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+# Live handles, closed at interpreter exit (batches first, then graphs)
+# while the HIP runtime is still up, so that no device memory, captured
+# graph or stream is released from a finaliser during runtime teardown.
+_live_graphs = weakref.WeakSet()
+_live_batches = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_handles():
+    for b in list(_live_batches):
+        try:
+            b.close()
+        except Exception:
+            pass
+    for g in list(_live_graphs):
+        try:
+            g.close()
+        except Exception:
+            pass
 
 
 def opts(precision="fp64", rtol=1e-10, inner_rtol=1e-5, max_iter=20000, max_refine=30,
@@ -70,24 +113,44 @@ def opts(precision="fp64", rtol=1e-10, inner_rtol=1e-5, max_iter=20000, max_refi
 
 
 class Graph:
-    """Device-resident graph handle built from a host CSR (symmetric, both
-    directions stored; weights None for unit weights)."""
+    """Device-resident graph handle built from a symmetric CSR (both
+    directions stored; weights None for unit weights).  The arrays may be
+    host arrays (NumPy or anything array-like) or CUDA tensors (int64
+    row_ptr, int32 col_idx, float64 weights), which the library reads in
+    place."""
 
     def __init__(self, row_ptr, col_idx, weights=None, n=None):
         lib = load()
-        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
-        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
-        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
-        self.n = int(rp.size - 1 if n is None else n)
-        self.nnz_in = int(ci.size)
+        torch = _torch()
+        on_dev = isinstance(row_ptr, torch.Tensor) and row_ptr.is_cuda
+        if on_dev:
+            rp = row_ptr.to(dtype=torch.int64).contiguous()
+            ci = torch.as_tensor(col_idx, device=rp.device).to(dtype=torch.int32).contiguous()
+            w = None if weights is None else \
+                torch.as_tensor(weights, device=rp.device).to(dtype=torch.float64).contiguous()
+            nrp, nnz = rp.numel(), ci.numel()
+            ptrs = (_ptr(rp), _ptr(ci), None if w is None else _ptr(w))
+            flags = _abi.NVD_PTR_DEVICE
+        else:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+            w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+            nrp, nnz = rp.size, ci.size
+            ptrs = (rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+                    None if w is None else w.ctypes.data_as(C.c_void_p))
+            flags = _abi.NVD_PTR_HOST
+        if w is not None and (w.numel() if on_dev else w.size) != nnz:
+            raise ValueError("weights must have one entry per col_idx entry")
+        self.n = int(nrp - 1 if n is None else n)
+        if self.n != nrp - 1:
+            raise ValueError("row_ptr must have n + 1 entries")
+        self.nnz_in = int(nnz)
         h = C.c_void_p()
-        st = lib.nvd_graph_create(self.n, self.nnz_in, rp.ctypes.data_as(C.c_void_p),
-                                  ci.ctypes.data_as(C.c_void_p),
-                                  None if w is None else w.ctypes.data_as(C.c_void_p),
-                                  _stream(), C.byref(h))
+        st = lib.nvd_graph_create_ex(self.n, self.nnz_in, *ptrs, flags, _stream(), C.byref(h))
         check(st, "nvd_graph_create")
         self._h = h
         self.weighted = w is not None
+        _live_graphs.add(self)
 
     @classmethod
     def from_csr(cls, row_ptr, col_idx, weights=None):
@@ -122,12 +185,23 @@ class Graph:
 
     # -- operator -----------------------------------------------------------
     def laplacian_apply(self, X, out=None):
+        """Y = L X for a CUDA tensor X (n,) or (n, k), float64 or float32;
+        out: optional preallocated Y of the same shape and dtype."""
         torch = _torch()
+        if not isinstance(X, torch.Tensor) or not X.is_cuda:
+            raise ValueError("X must be a CUDA tensor")
         if X.dim() == 1:
             X = X.reshape(-1, 1)
-        assert X.is_cuda and X.shape[0] == self.n and X.stride(1) == 1
+            if out is not None:
+                out = out.reshape(-1, 1)
+        if X.dim() != 2 or X.shape[0] != self.n:
+            raise ValueError(f"X must be ({self.n},) or ({self.n}, k)")
+        if X.dtype not in (torch.float64, torch.float32):
+            raise ValueError("X must be float64 or float32")
+        if X.stride(1) != 1 or X.stride(0) < X.shape[1]:
+            X = X.contiguous()
         dt = {torch.float64: NVD_DT_F64, torch.float32: NVD_DT_F32}[X.dtype]
-        Y = torch.empty_like(X) if out is None else out
+        Y = torch.empty_like(X) if out is None else _check_out(out, "out", X.shape, X.dtype)
         check(load().nvd_laplacian_apply(self._h, dt, X.shape[1], _ptr(X), X.stride(0),
                                          _ptr(Y), Y.stride(0), _stream()),
               "nvd_laplacian_apply")
@@ -147,23 +221,32 @@ class Graph:
     # -- distances ----------------------------------------------------------
     def distances(self, P, Q, precision="fp64", rtol=1e-10, inner_rtol=1e-5, max_iter=20000,
                   max_refine=30, tile_k=0, return_x=False, X0=None, raise_on_noconv=False,
-                  precond="jacobi"):
+                  precond="jacobi", out="d"):
         """Returns (d, X or None, info list).  P, Q: (n, k) or (n,) float64.
         precond: "jacobi" (the diagonal), "tree" (a spanning forest, solved
         exactly) or "auto" (the forest when at most n/100 edges lie off it,
-        else the diagonal)."""
+        else the diagonal).  X0: starting guess, (n, k) like P.
+        out: "d" for distances, "dsq" for their squares."""
         torch = _torch()
         P = _as_dev64(P, "P")
         Q = _as_dev64(Q, "Q")
         if P.shape != Q.shape or P.shape[0] != self.n:
             raise ValueError(f"P, Q must both be ({self.n}, k)")
+        if out not in ("d", "dsq"):
+            raise ValueError("out must be 'd' or 'dsq'")
         k = P.shape[1]
         o = opts(precision, rtol, inner_rtol, max_iter, max_refine, tile_k, X0 is not None, precond)
+        if out == "dsq":
+            o.flags |= _abi.NVD_OUT_DSQ
         d = torch.empty(k, dtype=torch.float64, device=P.device)
         X = None
-        if return_x or X0 is not None:
-            X = X0.clone().contiguous() if X0 is not None else \
-                torch.empty_like(P)
+        if X0 is not None:
+            X0 = _as_dev64(X0, "X0")
+            if X0.shape != P.shape:
+                raise ValueError(f"X0 must have the shape of P, {tuple(P.shape)}")
+            X = X0.clone()
+        elif return_x:
+            X = torch.empty_like(P)
         info = (PairInfo * k)()
         st = load().nvd_distances(self._h, k, _ptr(P), _ptr(Q), P.stride(0), C.byref(o),
                                   _ptr(d), _ptr(X), X.stride(0) if X is not None else 0,
@@ -204,22 +287,65 @@ class Graph:
         return t.value, nl.value
 
     def set_weights(self, w):
-        """Replace the edge weights (device float64, input CSR order)."""
+        """Replace the edge weights (float64, input CSR order)."""
         torch = _torch()
-        w = w.detach().to(device="cuda", dtype=torch.float64).contiguous()
-        assert w.numel() == self.nnz_in
+        w = torch.as_tensor(w).detach().to(device="cuda", dtype=torch.float64).reshape(-1).contiguous()
+        if w.numel() != self.nnz_in:
+            raise ValueError(f"w must have {self.nnz_in} entries (one per input CSR entry)")
         check(load().nvd_graph_set_weights(self._h, _ptr(w), _stream()), "nvd_graph_set_weights")
         self.weighted = True
+
+    def _gscale(self, gscale, k, device):
+        torch = _torch()
+        g = torch.as_tensor(gscale).to(device=device, dtype=torch.float64).reshape(-1).contiguous()
+        if g.numel() != k:
+            raise ValueError(f"gscale must have one entry per column ({k})")
+        return g
 
     def grad_weights(self, X, gscale):
         """-1/2 sum_j g_j (x_i - x_c)^2 for every input CSR entry (i, c)."""
         torch = _torch()
         X = _as_dev64(X, "X")
-        g = gscale.to(device=X.device, dtype=torch.float64).contiguous()
+        if X.shape[0] != self.n:
+            raise ValueError(f"X must be ({self.n}, k)")
+        g = self._gscale(gscale, X.shape[1], X.device)
         out = torch.empty(self.nnz_in, dtype=torch.float64, device=X.device)
         check(load().nvd_grad_weights(self._h, X.shape[1], _ptr(X), X.stride(0), _ptr(g),
                                       _ptr(out), _stream()), "nvd_grad_weights")
         return out
+
+    def grad_vectors(self, X, gscale, want_p=True, want_q=True):
+        """(2 X diag(g), -2 X diag(g)): the gradients of sum_j g_j d_j^2 with
+        respect to P and Q (None where not wanted)."""
+        torch = _torch()
+        X = _as_dev64(X, "X")
+        if X.shape[0] != self.n:
+            raise ValueError(f"X must be ({self.n}, k)")
+        k = X.shape[1]
+        g = self._gscale(gscale, k, X.device)
+        GP = torch.empty_like(X) if want_p else None
+        GQ = torch.empty_like(X) if want_q else None
+        if GP is None and GQ is None:
+            return None, None
+        check(load().nvd_grad_vectors(self._h, k, _ptr(X), X.stride(0), _ptr(g), _ptr(GP),
+                                      GP.stride(0) if GP is not None else 0, _ptr(GQ),
+                                      GQ.stride(0) if GQ is not None else 0, _stream()),
+              "nvd_grad_vectors")
+        return GP, GQ
+
+
+def grad_scale_from_d(g_d, d):
+    """g_d / (2 d) where d > 0, else 0: an upstream gradient on distances
+    turned into the scale on their squares (computed by the library)."""
+    torch = _torch()
+    d = torch.as_tensor(d).to(device="cuda", dtype=torch.float64).reshape(-1).contiguous()
+    g = torch.as_tensor(g_d).to(device=d.device, dtype=torch.float64).reshape(-1).contiguous()
+    if g.numel() != d.numel():
+        raise ValueError("g_d and d must have the same length")
+    out = torch.empty_like(d)
+    check(load().nvd_grad_scale_from_d(d.numel(), _ptr(g), _ptr(d), _ptr(out), _stream()),
+          "nvd_grad_scale_from_d")
+    return out
 
 
 class Batch:
@@ -234,6 +360,7 @@ class Batch:
               "nvd_batch_create")
         self._h = h
         self.ns = [g.n for g in self.graphs]
+        _live_batches.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -282,7 +409,11 @@ class Batch:
         else:
             ks, Pf, Qf = packed
         K = int(ks.sum())
-        d = out if out is not None else torch.empty(K, dtype=torch.float64, device="cuda")
+        if len(ks) != len(self.graphs) or Pf.numel() != Qf.numel() or \
+                Pf.numel() != int(sum(n * k for n, k in zip(self.ns, ks))):
+            raise ValueError("packed P, Q must hold an (n_g, k_g) block for every graph of the batch")
+        d = torch.empty(K, dtype=torch.float64, device="cuda") if out is None else \
+            _check_out(out, "out", (K,), torch.float64)
         X = torch.empty_like(Pf) if return_x else None
         info = (PairInfo * K)()
         o = opts(precision, rtol, inner_rtol, max_iter, max_refine)
@@ -320,4 +451,4 @@ def distance(g: Graph, p, q, **kw):
     return d, info
 
 
-from .autograd import DistanceSq, distance_sq, distance_t  # noqa: E402,F401
+from .autograd import DistanceSq, Distance, distance_sq, distance_t  # noqa: E402,F401

@@ -16,6 +16,8 @@ NVD_WARM_START = 1
 NVD_BATCH_PERSISTENT = 2
 NVD_PRECOND_TREE = 4
 NVD_PRECOND_AUTO = 8
+NVD_OUT_DSQ = 16
+NVD_PTR_HOST, NVD_PTR_DEVICE = 0, 1
 
 
 class NvdOpts(C.Structure):
@@ -49,6 +51,7 @@ SIGNATURES = {
     "nvd_last_error": (C.c_char_p, []),
     "nvd_opts_default": (_I32, [C.POINTER(NvdOpts)]),
     "nvd_graph_create": (_I32, [_I64, _I64, _P, _P, _P, _P, C.POINTER(_P)]),
+    "nvd_graph_create_ex": (_I32, [_I64, _I64, _P, _P, _P, C.c_uint32, _P, C.POINTER(_P)]),
     "nvd_graph_destroy": (_I32, [_P]),
     "nvd_graph_stats": (_I32, [_P, C.POINTER(Stats)]),
     "nvd_graph_query": (_I32, [_P, _P, _P]),
@@ -59,6 +62,8 @@ SIGNATURES = {
     "nvd_pairwise": (_I32, [_P, _I32, _P, _I64, C.POINTER(NvdOpts), _P, _I64, _P, _I64,
                              _P, _P]),
     "nvd_grad_weights": (_I32, [_P, _I32, _P, _I64, _P, _P, _P]),
+    "nvd_grad_vectors": (_I32, [_P, _I32, _P, _I64, _P, _P, _I64, _P, _I64, _P]),
+    "nvd_grad_scale_from_d": (_I32, [_I32, _P, _P, _P, _P]),
     "nvd_graph_set_weights": (_I32, [_P, _P, _P]),
     "nvd_batch_create": (_I32, [_I32, _P, _P, C.POINTER(_P)]),
     "nvd_batch_destroy": (_I32, [_P]),

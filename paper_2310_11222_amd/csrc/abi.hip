@@ -1,6 +1,7 @@
 // The extern "C" entry points declared in include/nvd.h: argument checks,
 // tiling of the k pairs, and the edge-weight adjoint kernel.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <vector>
 
@@ -44,18 +45,44 @@ __global__ __launch_bounds__(kBS) void k_grad_w(int n, const int* rp, const int*
   }
 }
 
-// New edge weights from a device array in the input CSR order: every
-// internal entry takes its value, and the value is checked (finite, > 0,
-// equal to the mirror entry's).  flag bit 1: bad value, bit 2: asymmetric.
-__global__ void k_set_weights(int n, const int* rp, const int* ci, const int* in_pos,
-                              const double* w_in, double* w64, float* w32, int* flag) {
+// Adjoint with respect to the node vectors: d(sum_j g_j d_j^2)/dP = 2 X
+// diag(g) and d/dQ its negative (x_j = L^+ delta_j is the saved solution;
+// L^+ is symmetric, so no second solve is needed).  Either output may be null.
+__global__ __launch_bounds__(kBS) void k_grad_vec(int n, int k, const double* __restrict__ X,
+                                                  long ldx, const double* __restrict__ gs,
+                                                  double* __restrict__ GP, long ldp,
+                                                  double* __restrict__ GQ, long ldq) {
+  const long tot = (long)n * k;
+  for (long e = (long)blockIdx.x * kBS + threadIdx.x; e < tot; e += (long)gridDim.x * kBS) {
+    const long i = e / k;
+    const int c = (int)(e % k);
+    const double v = 2.0 * gs[c] * X[i * ldx + c];
+    if (GP) GP[i * ldp + c] = v;
+    if (GQ) GQ[i * ldq + c] = -v;
+  }
+}
+
+// Upstream gradient on d turned into the scale on d^2: dd/d(d^2) = 1/(2d),
+// defined as 0 where d = 0 (d is not differentiable there; the zero vector
+// is the minimum-norm subgradient).
+__global__ void k_grad_scale_d(int k, const double* __restrict__ g, const double* __restrict__ d,
+                               double* __restrict__ gs) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  const double dj = d[j];
+  gs[j] = dj > 0.0 ? g[j] / (2.0 * dj) : 0.0;
+}
+
+// New edge weights from a device array in the input CSR order, checked
+// before anything is replaced: every value finite and > 0 and equal to its
+// mirror entry's.  flag bit 1: bad value, bit 2: asymmetric.
+__global__ void k_check_weights(int n, const int* rp, const int* ci, const int* in_pos,
+                                const double* w_in, int* flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   for (int e = rp[i]; e < rp[i + 1]; ++e) {
     const double v = w_in[in_pos ? in_pos[e] : e];
     if (!(v > 0.0) || !isfinite(v)) atomicOr(flag, 1);
-    w64[e] = v;
-    w32[e] = (float)v;
     const int j = ci[e];
     int lo = rp[j], hi = rp[j + 1];
     while (lo < hi) {                  // mirror entry (j, i)
@@ -67,6 +94,16 @@ __global__ void k_set_weights(int n, const int* rp, const int* ci, const int* in
     }
     if (lo >= rp[j + 1] || ci[lo] != i || w_in[in_pos ? in_pos[lo] : lo] != v) atomicOr(flag, 2);
   }
+}
+
+// Commit checked weights: every internal entry takes its input value.
+__global__ void k_set_weights(int nnz, const int* in_pos, const double* w_in, double* w64,
+                              float* w32) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const double v = w_in[in_pos ? in_pos[e] : e];
+  w64[e] = v;
+  w32[e] = (float)v;
 }
 
 __global__ void k_degree_refresh(int n, const int* rp, const double* w64, double* deg64,
@@ -148,19 +185,47 @@ nvd_status nvd_opts_default(nvd_opts* o) {
   return NVD_OK;
 }
 
-nvd_status nvd_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr,
-                            const int32_t* col_idx, const double* weights, void* stream,
-                            nvd_graph** out) {
+nvd_status nvd_graph_create_ex(int64_t n, int64_t nnz, const int64_t* row_ptr,
+                               const int32_t* col_idx, const double* weights, uint32_t flags,
+                               void* stream, nvd_graph** out) {
   set_error("");
   if (!out) {
     set_error("nvd_graph_create: out is NULL");
     return NVD_E_ARG;
   }
   *out = nullptr;
+  if (flags & ~(uint32_t)NVD_PTR_DEVICE) {
+    set_error("nvd_graph_create_ex: unknown flag");
+    return NVD_E_ARG;
+  }
   DevGraph* g = nullptr;
-  NVD_TRY(graph_create(n, nnz, row_ptr, col_idx, weights, as_stream(stream), &g));
+  if (flags & NVD_PTR_DEVICE) {
+    // device arrays: staged to the host, where validation and set-up run
+    if (n < 1 || nnz < 0 || n >= INT32_MAX || nnz >= INT32_MAX || !row_ptr || (nnz > 0 && !col_idx)) {
+      set_error("nvd_graph_create_ex: need 1 <= n < 2^31, 0 <= nnz < 2^31 and non-NULL arrays");
+      return NVD_E_ARG;
+    }
+    std::vector<int64_t> rp(n + 1);
+    std::vector<int32_t> ci(std::max<int64_t>(nnz, 1));
+    std::vector<double> w(weights ? std::max<int64_t>(nnz, 1) : 0);
+    hipStream_t s = as_stream(stream);
+    NVD_HIP(hipStreamSynchronize(s));
+    NVD_HIP(hipMemcpy(rp.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+    if (nnz > 0) NVD_HIP(hipMemcpy(ci.data(), col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+    if (weights && nnz > 0)
+      NVD_HIP(hipMemcpy(w.data(), weights, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+    NVD_TRY(graph_create(n, nnz, rp.data(), ci.data(), weights ? w.data() : nullptr, s, &g));
+  } else {
+    NVD_TRY(graph_create(n, nnz, row_ptr, col_idx, weights, as_stream(stream), &g));
+  }
   *out = new nvd_graph{g};
   return NVD_OK;
+}
+
+nvd_status nvd_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col_idx, const double* weights, void* stream,
+                            nvd_graph** out) {
+  return nvd_graph_create_ex(n, nnz, row_ptr, col_idx, weights, NVD_PTR_HOST, stream, out);
 }
 
 nvd_status nvd_graph_destroy(nvd_graph* g) {
@@ -275,6 +340,7 @@ nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double*
   sp.max_refine = o.max_refine;
   sp.warm = (o.flags & NVD_WARM_START) != 0;
   sp.tree = use_tree(g, o.flags);
+  sp.out_dsq = (o.flags & NVD_OUT_DSQ) != 0;
   int tile = o.tile_k;
   if (tile == 0) tile = choose_tile(g, k, o.precision, s);
   std::vector<nvd_pair_info> hinfo(k);
@@ -317,25 +383,42 @@ nvd_status nvd_graph_set_weights(nvd_graph* h, const double* w, void* stream) {
   }
   DevGraph* g = h->g;
   hipStream_t s = as_stream(stream);
-  if (!g->w64) {
-    NVD_HIP(hipMalloc((void**)&g->w64, sizeof(double) * std::max(g->nnz, 1)));
-    NVD_HIP(hipMalloc((void**)&g->w32, sizeof(float) * std::max(g->nnz, 1)));
-    g->bytes += (int64_t)12 * std::max(g->nnz, 1);
-  }
+  // 1. check the new values; the graph is left untouched if they are rejected
   int* flag = nullptr;
   NVD_HIP(hipMalloc((void**)&flag, sizeof(int)));
   int hflag = 0;
   hipError_t e = hipMemcpyAsync(flag, &hflag, sizeof(int), hipMemcpyHostToDevice, s);
   const int grid = (g->n + 255) / 256;
   if (e == hipSuccess) {
-    k_set_weights<<<grid, 256, 0, s>>>(g->n, g->rp, g->ci, g->in_pos, w, g->w64, g->w32, flag);
-    k_degree_refresh<<<grid, 256, 0, s>>>(g->n, g->rp, g->w64, g->deg64, g->deg32, g->invd64,
-                                          g->invd32);
+    k_check_weights<<<grid, 256, 0, s>>>(g->n, g->rp, g->ci, g->in_pos, w, flag);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(flag);
+  if (e != hipSuccess) {
+    set_error(std::string("nvd_graph_set_weights: ") + hipGetErrorString(e));
+    return NVD_E_DEVICE;
+  }
+  if (hflag) {
+    set_error(std::string("nvd_graph_set_weights: ") +
+              ((hflag & 1) ? "a weight is not a finite positive number" : "") +
+              ((hflag & 3) == 3 ? "; " : "") +
+              ((hflag & 2) ? "weights of an entry and its mirror differ" : ""));
+    return NVD_E_GRAPH;
+  }
+  // 2. commit: weights, degrees and their inverses
+  if (!g->w64) {
+    NVD_HIP(hipMalloc((void**)&g->w64, sizeof(double) * std::max(g->nnz, 1)));
+    NVD_HIP(hipMalloc((void**)&g->w32, sizeof(float) * std::max(g->nnz, 1)));
+    g->bytes += (int64_t)12 * std::max(g->nnz, 1);
+  }
+  if (g->nnz > 0)
+    k_set_weights<<<(g->nnz + 255) / 256, 256, 0, s>>>(g->nnz, g->in_pos, w, g->w64, g->w32);
+  k_degree_refresh<<<grid, 256, 0, s>>>(g->n, g->rp, g->w64, g->deg64, g->deg32, g->invd64,
+                                        g->invd32);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     set_error(std::string("nvd_graph_set_weights: ") + hipGetErrorString(e));
     return NVD_E_DEVICE;
@@ -351,13 +434,34 @@ nvd_status nvd_graph_set_weights(nvd_graph* h, const double* w, void* stream) {
     return NVD_E_DEVICE;
   }
   g->h_w.resize(g->nnz);
-  if (hflag) {
-    set_error(std::string("nvd_graph_set_weights: ") +
-              ((hflag & 1) ? "a weight is not a finite positive number" : "") +
-              ((hflag & 3) == 3 ? "; " : "") +
-              ((hflag & 2) ? "weights of an entry and its mirror differ" : ""));
-    return NVD_E_GRAPH;
+  return NVD_OK;
+}
+
+nvd_status nvd_grad_vectors(nvd_graph* h, int32_t k, const double* X, int64_t ldx,
+                            const double* gscale, double* GP, int64_t ldp, double* GQ,
+                            int64_t ldq, void* stream) {
+  set_error("");
+  if (!h || !X || !gscale || (!GP && !GQ) || k < 1 || ldx < k || (GP && ldp < k) ||
+      (GQ && ldq < k)) {
+    set_error("nvd_grad_vectors: bad argument (NULL pointer, k < 1 or ld < k)");
+    return NVD_E_ARG;
   }
+  const int n = h->g->n;
+  const long grid = std::min<long>(std::max<long>(((long)n * k + kBS - 1) / kBS, 1), 4096);
+  k_grad_vec<<<grid, kBS, 0, as_stream(stream)>>>(n, k, X, ldx, gscale, GP, ldp, GQ, ldq);
+  NVD_HIP(hipGetLastError());
+  return NVD_OK;
+}
+
+nvd_status nvd_grad_scale_from_d(int32_t k, const double* g_d, const double* d, double* gscale,
+                                 void* stream) {
+  set_error("");
+  if (!g_d || !d || !gscale || k < 1) {
+    set_error("nvd_grad_scale_from_d: bad argument (NULL pointer or k < 1)");
+    return NVD_E_ARG;
+  }
+  k_grad_scale_d<<<(k + 255) / 256, 256, 0, as_stream(stream)>>>(k, g_d, d, gscale);
+  NVD_HIP(hipGetLastError());
   return NVD_OK;
 }
 

@@ -80,6 +80,7 @@ struct BatchArgs {
   double rtol2, irtol2;
   int max_iter, max_refine;
   int* err;
+  unsigned spin_limit;        // polls of a team barrier before it gives up
   unsigned long long* trace;  // [2G] start/end wall-clock ticks per graph, or null
 };
 
@@ -106,7 +107,16 @@ struct Team {
   int B;
   int parity;
   int* err;
+  unsigned spin_limit;
 };
+
+// The launch's failure word: set by a barrier wait that gave up.  Once it is
+// set every barrier returns at once and every solve loop exits, so the
+// kernel ends after a bounded amount of work and the host reports the
+// failure (the outputs of that call are then meaningless).
+__device__ __forceinline__ bool team_failed(const Team& tm) {
+  return __hip_atomic_load(tm.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
 
 __device__ __forceinline__ void team_sync(Team& tm) {
   if (tm.S == 1) {
@@ -119,13 +129,17 @@ __device__ __forceinline__ void team_sync(Team& tm) {
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(tm.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned target = tm.epoch * (unsigned)tm.S;
-    unsigned spins = 0;
-    while (__hip_atomic_load(tm.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
-      if (++spins > kSpinLimit) {
+    // at most spin_limit polls (0: give up at once, which makes the
+    // failure path testable), and none once the launch has failed
+    for (unsigned spins = 0;; ++spins) {
+      if (spins >= tm.spin_limit) {
         __hip_atomic_store(tm.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
+      if (__hip_atomic_load(tm.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target ||
+          team_failed(tm))
+        break;
+      __builtin_amdgcn_s_sleep(2);
     }
   }
   __syncthreads();
@@ -218,6 +232,12 @@ struct Lds {
   int *act, *oact, *it, *itc, *ref, *stat;          // [kMaxTile] each
   int* cnt;          // [2]: active, open
 };
+
+// Thread 0 folds the launch's failure word into a loop count (callers
+// __syncthreads before reading it): a failed launch leaves its loops.
+__device__ __forceinline__ int unless_failed(const Team& tm, int count) {
+  return team_failed(tm) ? 0 : count;
+}
 
 // Laplacian apply on rows [lo, hi) of one graph.
 //   EPI_CG:    y = L x (V), acc[0] += x.y          (x = p, y = q)
@@ -485,7 +505,7 @@ __device__ __noinline__ void solve_graph(const BatchArgs& a, int gi, Team& tm, c
         }
         no += L.oact[q];
       }
-      L.cnt[1] = no;
+      L.cnt[1] = unless_failed(tm, no);
     }
     __syncthreads();
     if (L.cnt[1] == 0) break;
@@ -523,7 +543,7 @@ __device__ __noinline__ void solve_graph(const BatchArgs& a, int gi, Team& tm, c
       if (t == 0) {
         int na = 0;
         for (int q = 0; q < T; ++q) na += L.act[q];
-        L.cnt[0] = na;
+        L.cnt[0] = unless_failed(tm, na);
       }
       __syncthreads();
       if (L.cnt[0] == 0) break;
@@ -726,7 +746,7 @@ __device__ __noinline__ void solve_graph(const BatchArgs& a, int gi, Team& tm, c
     double dsq = bb > 0.0 ? bx + xr : 0.0;
     a.d_out[gd.out_off + t] = sqrt(dsq > 0.0 ? dsq : 0.0);
     nvd_pair_info pi;
-    pi.status = L.stat[t];
+    pi.status = team_failed(tm) ? (int)NVD_E_DEVICE : L.stat[t];
     pi.iters = L.it[t];
     pi.refine_steps = L.ref[t];
     pi.reserved = 0;
@@ -781,6 +801,7 @@ __global__ __launch_bounds__(BBS, 4) void k_batch(BatchArgs a) {
   tm.B = a.B;
   tm.parity = 0;
   tm.err = a.err;
+  tm.spin_limit = a.spin_limit;
   if (gi >= 0) {
     if (tm.S > 1)
       solve_graph<T, V, true>(a, gi, tm, L);
@@ -1126,6 +1147,15 @@ static nvd_status run_batch(nvd_batch* b, const std::vector<int>& ks, const doub
   a.max_iter = o.max_iter;
   a.max_refine = mixed ? o.max_refine : std::max(2, std::min(o.max_refine, 3));
   a.err = b->err;
+  // NVD_BATCH_SPIN_LIMIT: polls of a team barrier before it gives up (0 makes
+  // the first barrier of a multi-block team fail: the failure path can then
+  // be tested without a stalled team)
+  a.spin_limit = kSpinLimit;
+  if (const char* sl = std::getenv("NVD_BATCH_SPIN_LIMIT")) {
+    const long v = std::strtol(sl, nullptr, 10);
+    if (v >= 0 && v < (long)kSpinLimit) a.spin_limit = (unsigned)v;
+    key.push_back((int)a.spin_limit);
+  }
   const char* tr = std::getenv("NVD_BATCH_TRACE");
   if (tr && tr[0] == '1') {
     if (!b->trace) NVD_TRY(balloc(b, &b->trace, (size_t)2 * G));
@@ -1189,6 +1219,10 @@ static nvd_status run_batch(nvd_batch* b, const std::vector<int>& ks, const doub
   if (info_host)
     NVD_HIP(hipMemcpyAsync(info_host, b->info, sizeof(nvd_pair_info) * K, hipMemcpyDeviceToHost, s));
   NVD_HIP(hipStreamSynchronize(s));
+  if (*b->h_err) {
+    set_error("batched solver: a team barrier timed out (blocks not co-resident?)");
+    return NVD_E_DEVICE;
+  }
   if (info_host) {
     int off = 0;
     for (int i = 0; i < G; ++i) {
@@ -1197,10 +1231,6 @@ static nvd_status run_batch(nvd_batch* b, const std::vector<int>& ks, const doub
       if (itmax > 0) b->it_est[i] = itmax;
       off += ks[i];
     }
-  }
-  if (*b->h_err) {
-    set_error("batched solver: a team barrier timed out (blocks not co-resident?)");
-    return NVD_E_DEVICE;
   }
   return NVD_OK;
 }

@@ -611,7 +611,7 @@ __global__ void k_outer_check(int T, int n, double rtol2, int max_refine, ColSta
 // (L 1 = 0) and changes delta_bar^T x by -m sum(delta_bar) = 0, so only x^T r
 // changes, by -m sum(r).
 __global__ void k_finish(int T, int mark_open_noconv, ColState* cs, double* d_out,
-                         nvd_pair_info* info, int shift_n) {
+                         nvd_pair_info* info, int shift_n, int out_dsq) {
   const int t = threadIdx.x;
   if (t >= T) return;
   const double bx = cs->dots[0][t];
@@ -628,7 +628,8 @@ __global__ void k_finish(int T, int mark_open_noconv, ColState* cs, double* d_ou
   }
   int st = cs->status[t];
   if (mark_open_noconv && st == kStOk && cs->oactive[t]) st = kStNoconv;
-  d_out[t] = sqrt(dsq > 0.0 ? dsq : 0.0);
+  const double dsq0 = dsq > 0.0 ? dsq : 0.0;
+  d_out[t] = out_dsq ? dsq0 : sqrt(dsq0);
   nvd_pair_info pi;
   pi.status = st;
   pi.iters = cs->iters[t];
@@ -1099,7 +1100,7 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
     if (shift_n > 0) xm.dots_sum = ws->cs->dots[4];
     NVD_TILE_SWITCH(T, (k_xfinal<TT><<<grid, kBS, 0, s>>>(n, ws->x64, xm, X, ldx)));
   }
-  k_finish<<<1, 64, 0, s>>>(T, mixed ? 0 : 1, ws->cs, d_out, info_dev, shift_n);
+  k_finish<<<1, 64, 0, s>>>(T, mixed ? 0 : 1, ws->cs, d_out, info_dev, shift_n, sp.out_dsq ? 1 : 0);
   NVD_HIP(hipGetLastError());
   return NVD_OK;
 }

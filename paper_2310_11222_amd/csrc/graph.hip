@@ -450,7 +450,11 @@ static nvd_status build_graph(int64_t n64, int64_t nnz64, const int64_t* row_ptr
   chk(dalloc(&g->comp, n, by));
   chk(dalloc(&g->comp_perm, n, by));
   chk(dalloc(&g->comp_off, ncomp + 1, by));
-  if (self_loops > 0) chk(dalloc(&g->in_pos, nnz, by));
+  // the map to input positions is needed whenever it is not the identity:
+  // self-loops were dropped or some row was given unsorted
+  const bool all_sorted = std::all_of(sorted_row.begin(), sorted_row.end(), [](char c) { return c != 0; });
+  const bool need_pos = self_loops > 0 || !all_sorted;
+  if (need_pos) chk(dalloc(&g->in_pos, nnz, by));
   const int nseg = (int)seg_row.size();
   if (nseg > 0) {
     chk(dalloc(&g->long_buf, (size_t)5 * nseg, by));
@@ -471,7 +475,7 @@ static nvd_status build_graph(int64_t n64, int64_t nnz64, const int64_t* row_ptr
   up(g->comp, comp.data(), n * sizeof(int));
   up(g->comp_perm, perm.data(), n * sizeof(int));
   up(g->comp_off, comp_off.data(), (ncomp + 1) * sizeof(int));
-  if (self_loops > 0) up(g->in_pos, in_pos.data(), nnz * sizeof(int));
+  if (need_pos) up(g->in_pos, in_pos.data(), nnz * sizeof(int));
   if (nseg > 0 && st == NVD_OK) {
     int* lb = g->long_buf;
     up(lb + 0 * nseg, seg_row.data(), nseg * sizeof(int));

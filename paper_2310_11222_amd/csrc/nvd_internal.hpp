@@ -213,6 +213,7 @@ struct SolveParams {
   int grid;                 // SpMM short-row grid (0 = default)
   bool warm;
   bool tree;                // spanning-tree preconditioner instead of Jacobi
+  bool out_dsq;             // d_out receives d^2 instead of d
 };
 nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
                       const SolveParams& sp, double* d_out, double* X, int64_t ldx,

@@ -131,10 +131,18 @@ __global__ void k_gram_sum2(int m, const double* __restrict__ part2, double* __r
   Gt[e] = acc;
 }
 
+// A pair whose Gram-form d^2 is below this fraction of Gt_ii + Gt_jj has
+// lost that many digits to cancellation: it is evaluated again from the
+// column differences (k_pair_exact).  Rounding of the Gram entries is a few
+// eps of |Gt_ii| + |Gt_jj|, so the pairs kept lose at most ~1e-10 of d^2.
+constexpr double kCloseRel = 1e-5;
+
 // D_ij = sqrt(max(Gt_ii + Gt_jj - Gt_ij - Gt_ji, 0)), D_ii = 0; optionally the
-// symmetrised Gram matrix (Gt + Gt^T) / 2.
+// symmetrised Gram matrix (Gt + Gt^T) / 2.  Pairs i < j with heavy
+// cancellation are appended to close[] (count in *nclose).
 __global__ void k_pdist(int m, const double* __restrict__ Gt, double* __restrict__ D, long ldd,
-                        double* __restrict__ G, long ldg) {
+                        double* __restrict__ G, long ldg, int2* __restrict__ close,
+                        unsigned* __restrict__ nclose) {
   const long mm = (long)m * m;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < mm; e += (long)gridDim.x * blockDim.x) {
     const int i = (int)(e / m), j = (int)(e % m);
@@ -142,12 +150,61 @@ __global__ void k_pdist(int m, const double* __restrict__ Gt, double* __restrict
     double d = 0.0;
     if (i != j) {
       // (a + b) - (c + d): only commutative additions, so D_ij == D_ji exactly
-      const double dsq = (Gt[(long)i * m + i] + Gt[(long)j * m + j]) - (gij + gji);
+      const double gii = Gt[(long)i * m + i], gjj = Gt[(long)j * m + j];
+      const double dsq = (gii + gjj) - (gij + gji);
       d = sqrt(dsq > 0.0 ? dsq : 0.0);
+      if (i < j && dsq < kCloseRel * (fabs(gii) + fabs(gjj))) {
+        const unsigned slot = atomicAdd(nclose, 1u);
+        close[slot] = make_int2(i, j);
+      }
     }
     D[(long)i * ldd + j] = d;
     if (G) G[(long)i * ldg + j] = 0.5 * (gij + gji);
   }
+}
+
+// The quadratic form of a close pair from its column differences, with no
+// cancellation between large Gram entries:
+//   J = sum_r (vb_ri - vb_rj)(x_ri - x_rj) + (x_ri - x_rj)(r_ri - r_rj).
+// Block (p, s) sums rows [s*rows, (s+1)*rows) of pair p into part[p][s].
+constexpr int kExactSlices = 64;
+__global__ __launch_bounds__(256) void k_pair_exact(int n, int m, const double* __restrict__ Vb,
+                                                    const double* __restrict__ X,
+                                                    const double* __restrict__ R,
+                                                    const int2* __restrict__ close, int rows,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int2 pr = close[blockIdx.x];
+  const long r0 = (long)blockIdx.y * rows;
+  const long r1 = min((long)n, r0 + rows);
+  double acc = 0.0;
+  for (long r = r0 + threadIdx.x; r < r1; r += 256) {
+    const long o = r * m;
+    const double dv = Vb[o + pr.x] - Vb[o + pr.y];
+    const double dx = X[o + pr.x] - X[o + pr.y];
+    const double dr = R[o + pr.x] - R[o + pr.y];
+    acc += dv * dx + dx * dr;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long)blockIdx.x * kExactSlices + blockIdx.y] = sh[0];
+}
+
+// D_ij = D_ji = sqrt(max(J, 0)) from the slices' sums, added in slice order.
+__global__ void k_pair_fix(int nclose, const int2* __restrict__ close, const double* __restrict__ part,
+                           int slices, double* __restrict__ D, long ldd) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nclose) return;
+  double j = 0.0;
+  for (int s = 0; s < slices; ++s) j += part[(long)p * kExactSlices + s];
+  const double d = sqrt(j > 0.0 ? j : 0.0);
+  const int2 pr = close[p];
+  D[(long)pr.x * ldd + pr.y] = d;
+  D[(long)pr.y * ldd + pr.x] = d;
 }
 
 }  // namespace nvd
@@ -189,7 +246,10 @@ extern "C" nvd_status nvd_pairwise(nvd_graph* h, int32_t m, const double* V, int
   if (S < 1) S = 1;
   // device scratch, freed on return
   double* buf = nullptr;
-  const size_t nbuf = 3 * nm + (size_t)(S + kSumGroups + 1) * m * m + kMaxTile;
+  // (+ the close-pair list: m(m-1)/2 int2, a counter, and their partial sums
+  // in the space of part[], which is free again by then)
+  const size_t npairs = (size_t)m * (m - 1) / 2;
+  const size_t nbuf = 3 * nm + (size_t)(S + kSumGroups + 1) * m * m + kMaxTile + npairs + 1;
   NVD_HIP(hipMalloc((void**)&buf, nbuf * sizeof(double)));
   double* Vb = buf;
   double* X = Vb + nm;
@@ -198,6 +258,8 @@ extern "C" nvd_status nvd_pairwise(nvd_graph* h, int32_t m, const double* V, int
   double* part2 = part + (size_t)S * m * m;
   double* Gt = part2 + (size_t)kSumGroups * m * m;
   double* dscratch = Gt + (size_t)m * m;
+  int2* close = reinterpret_cast<int2*>(dscratch + kMaxTile);
+  unsigned* nclose = reinterpret_cast<unsigned*>(close + npairs);
   SolveParams sp{};
   sp.precision = o.precision;
   sp.rtol = o.rtol;
@@ -241,9 +303,26 @@ extern "C" nvd_status nvd_pairwise(nvd_graph* h, int32_t m, const double* V, int
     const int ge = (int)(((long)m * m + 255) / 256);
     k_gram_sum1<<<dim3(ge, kSumGroups), 256, 0, s>>>(m, S, part, part2);
     k_gram_sum2<<<ge, 256, 0, s>>>(m, part2, Gt);
-    k_pdist<<<std::max(g2, 1), 256, 0, s>>>(m, Gt, D, ldd, G, ldg);
-    hipError_t e = hipGetLastError();
+    hipError_t e = hipMemsetAsync(nclose, 0, sizeof(unsigned), s);
+    if (e == hipSuccess) {
+      k_pdist<<<std::max(g2, 1), 256, 0, s>>>(m, Gt, D, ldd, G, ldg, close, nclose);
+      e = hipGetLastError();
+    }
+    unsigned hclose = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hclose, nclose, sizeof(unsigned), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && hclose > 0) {
+      // close pairs again from their column differences; their partial sums
+      // (64 per pair) go to part2[], free once Gt is formed: it holds
+      // 64 m^2 > 64 m (m-1) / 2 doubles
+      const int slices = std::min(kExactSlices, std::max(1, (n + 4095) / 4096));
+      const int rows = (n + slices - 1) / slices;
+      const int cnt = (int)hclose;
+      k_pair_exact<<<dim3(cnt, slices), 256, 0, s>>>(n, m, Vb, X, R, close, rows, part2);
+      k_pair_fix<<<(cnt + 255) / 256, 256, 0, s>>>(cnt, close, part2, slices, D, ldd);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
     if (e != hipSuccess) {
       set_error(std::string("nvd_pairwise: ") + hipGetErrorString(e));
       st = NVD_E_DEVICE;

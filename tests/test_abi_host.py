@@ -107,3 +107,37 @@ def test_argument_errors():
     assert lib.nvd_laplacian_apply(None, 0, 1, None, 1, None, 1, None) == abi.NVD_E_ARG
     assert lib.nvd_opts_default(None) == abi.NVD_E_ARG
     assert lib.nvd_pairwise(None, 4, None, 4, None, None, 4, None, 0, None, None) == abi.NVD_E_ARG
+    # graph from device arrays: flag and argument checks come first
+    assert lib.nvd_graph_create_ex(3, 0, None, None, None, 4, None, C.byref(h)) == abi.NVD_E_ARG
+    assert lib.nvd_graph_create_ex(3, 6, None, None, None, abi.NVD_PTR_DEVICE, None,
+                                   C.byref(h)) == abi.NVD_E_ARG
+    assert lib.nvd_graph_create_ex(2 ** 31, 0, big.ctypes.data_as(C.c_void_p), None, None,
+                                   abi.NVD_PTR_DEVICE, None, C.byref(h)) == abi.NVD_E_ARG
+    # adjoint entry points
+    assert lib.nvd_grad_vectors(None, 1, None, 1, None, None, 1, None, 1, None) == abi.NVD_E_ARG
+    assert lib.nvd_grad_scale_from_d(0, None, None, None, None) == abi.NVD_E_ARG
+    assert lib.nvd_grad_weights(None, 1, None, 1, None, None, None) == abi.NVD_E_ARG
+
+
+def test_host_graph_create_ex_matches_create():
+    """nvd_graph_create_ex with NVD_PTR_HOST validates like nvd_graph_create
+    (the invalid graph is rejected before any device work)."""
+    lib, abi = _lib()
+    rp = np.array([0, 1, 1, 1], dtype=np.int64)
+    ci = np.array([1], dtype=np.int32)
+    h = C.c_void_p()
+    st = lib.nvd_graph_create_ex(3, 1, rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+                                 None, abi.NVD_PTR_HOST, None, C.byref(h))
+    assert st == abi.NVD_E_GRAPH
+    assert b"mirror" in lib.nvd_last_error()
+
+
+def test_binding_output_checks_on_host_tensors():
+    """The binding refuses an output buffer that is not a CUDA tensor before
+    the library is called (the check needs no GPU)."""
+    torch = pytest.importorskip("torch")
+    from paper_2310_11222_amd import _check_out
+    with pytest.raises(ValueError):
+        _check_out(torch.empty(4, dtype=torch.float64), "out", (4,), torch.float64)
+    with pytest.raises(ValueError):
+        _check_out(np.empty(4), "out", (4,), torch.float64)

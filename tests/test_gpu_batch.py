@@ -222,3 +222,32 @@ def test_tiles_across_widths(k, precision, persistent):
         assert rel_err(d[off:off + k], ref).max() <= tol, (g.n, k)
         off += k
     assert all(i["status"] == 0 for i in info)
+
+
+def test_persistent_barrier_failure_is_reported(monkeypatch):
+    """A team barrier that gives up (forced from the host: a spin limit of 0
+    makes the first barrier of a multi-block team fail at once) ends every
+    loop of the launch, which then exits normally; the call reports
+    NVD_E_DEVICE.  The next call, with the default limit, is correct again."""
+    import paper_2310_11222_amd as nvd
+    sizes = [60000] + [400] * 6
+    ks = [8] * len(sizes)
+    graphs, Ps, Qs = _mk_batch(31, sizes, ks)
+    dgs = [dev_graph(g) for g in graphs]
+    batch = nvd.Batch(dgs)
+    say("batch barrier failure")
+    monkeypatch.setenv("NVD_BATCH_SPIN_LIMIT", "0")
+    with pytest.raises(nvd.NvdError) as ei:
+        batch.distances(Ps, Qs, precision="mixed", rtol=1e-8, persistent=True)
+    assert ei.value.status == 6          # NVD_E_DEVICE
+    monkeypatch.delenv("NVD_BATCH_SPIN_LIMIT")
+    say("batch after barrier failure")
+    d, _, info = batch.distances(Ps, Qs, precision="mixed", rtol=1e-8, persistent=True)
+    d = d.cpu().numpy()
+    ref0 = oracle.ge_pcg(graphs[0].n, graphs[0].row_ptr, graphs[0].col_idx, graphs[0].w,
+                         Ps[0], Qs[0])["d"]
+    assert rel_err(d[:8], ref0).max() <= 1e-6
+    assert all(i["status"] == 0 for i in info)
+    batch.close()
+    for dg in dgs:
+        dg.close()

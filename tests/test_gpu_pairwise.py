@@ -109,3 +109,28 @@ def test_pairwise_ba_2e5_sampled_pairs():
     r = oracle.ge_pcg(g.n, g.row_ptr, g.col_idx, g.w, V[:, iu[pick]], V[:, ju[pick]])
     assert rel_err(D[iu[pick], ju[pick]], r["d"]).max() <= 1e-6
     assert np.array_equal(D, D.T)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
+def test_pairwise_near_duplicate_columns(precision, tol):
+    """Columns 4..7 are columns 0..3 plus a 1e-4 perturbation: the pair
+    distances among them are ~1e-4 of the vectors' own L^+ norms, so the
+    Gram-difference form G_ii + G_jj - G_ij - G_ji cancels ~8 digits.  Every
+    pair, close or not, must meet the relative bound."""
+    rng = np.random.default_rng(77)
+    g = barabasi_albert(900, 3, rng)
+    g = g.with_weights(rng.uniform(0.5, 2.0, g.num_edges))
+    base = np.where(rng.random((g.n, 4)) < 0.2, rng.random((g.n, 4)), 0.0)
+    V = np.concatenate([base, base + 1e-4 * rng.standard_normal((g.n, 4))], axis=1)
+    say("pairwise near duplicates", precision)
+    dg = dev_graph(g)
+    D, _, info = dg.pairwise(V, precision=precision, rtol=1e-10 if precision == "fp64" else 1e-8)
+    D = D.cpu().numpy()
+    ref = oracle.pairwise_dense(g.n, g.row_ptr, g.col_idx, g.w, V)
+    off = ~np.eye(V.shape[1], dtype=bool)
+    assert np.array_equal(D, D.T)
+    assert ref[off].min() > 0
+    e = rel_err(D[off], ref[off])
+    assert e.max() <= tol, e.max()
+    # the close pairs (i, i + 4) are far below the others
+    assert max(ref[i, i + 4] for i in range(4)) < 1e-2 * ref[0, 1]

@@ -2,8 +2,13 @@
 oracle, element by element on the same seeded inputs.
 
 Tolerances: FP64 path <= 1e-8 relative error per distance, mixed path
-<= 1e-6 (the targets the workloads state); Laplacian apply: normwise
-relative 1e-13 (FP64) / 1e-5 (FP32)."""
+<= 1e-6 (the targets the workloads state).  Laplacian apply, per element:
+|Y_ic - (L X)_ic| <= tol * (|L| |X|)_ic with tol = 1e-13 (FP64) and 2e-6
+(FP32).  (|L| |X|)_ic = sum_u w_iu (|x_ic| + |x_uc|) bounds every term of
+the row's sum, so this is the backward-error form of a summation of deg_i + 1
+terms: deg * eps is 2.9e-13 (FP64) and 1.6e-4 (FP32) at the hub's 2,600
+neighbours in the worst case; the bounds used hold with the error growing
+like sqrt(deg) * eps, as in a summation with independent roundings."""
 import numpy as np
 import pytest
 
@@ -44,17 +49,27 @@ def test_laplacian_apply_matches_oracle(weighted, k):
     X = rng.standard_normal((g.n, k))
     L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, g.w)
     want = L @ X
+    absL = abs(L)
+    scale64 = absL @ np.abs(X)
     Y = dg.laplacian_apply(to_dev(X)).cpu().numpy()
-    assert np.linalg.norm(Y - want) <= 1e-13 * np.linalg.norm(want)
+    bad = np.abs(Y - want) > 1e-13 * scale64
+    assert not bad.any(), (np.argwhere(bad)[:5], np.max(np.abs(Y - want) / np.maximum(scale64, 1e-300)))
+    # FP32: input and weights are rounded to FP32 first, as the kernel sees them
+    X32 = X.astype(np.float32).astype(np.float64)
+    w32 = None if g.w is None else g.w.astype(np.float32).astype(np.float64)
+    L32 = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, w32)
+    want32 = L32 @ X32
     Y32 = dg.laplacian_apply(to_dev(X).float()).cpu().numpy()
-    assert np.linalg.norm(Y32 - want) <= 1e-5 * np.linalg.norm(want)
+    scale32 = abs(L32) @ np.abs(X32)
+    bad = np.abs(Y32 - want32) > 2e-6 * scale32
+    assert not bad.any(), (np.argwhere(bad)[:5], np.max(np.abs(Y32 - want32) / np.maximum(scale32, 1e-300)))
     # strided input / output (leading dimension > k)
     Xs = torch.zeros((g.n, k + 5), dtype=torch.float64, device="cuda")
     Xs[:, :k] = to_dev(X)
     Ys = torch.full((g.n, k + 3), 7.0, dtype=torch.float64, device="cuda")
     dg.laplacian_apply(Xs[:, :k], out=Ys[:, :k])
     Ys = Ys.cpu().numpy()
-    assert np.linalg.norm(Ys[:, :k] - want) <= 1e-13 * np.linalg.norm(want)
+    assert not (np.abs(Ys[:, :k] - want) > 1e-13 * scale64).any()
     assert np.all(Ys[:, k:] == 7.0)
 
 
@@ -210,7 +225,7 @@ def test_degenerate_pairs():
         assert d[1] == 0.0 or d[1] < 1e-12
         assert d[3] == 0.0
         ref = oracle.ge_dense(g.n, g.row_ptr, g.col_idx, None, P[:, 2:3], Q[:, 2:3])["d"][0]
-        assert abs(d[2] - ref) <= 1e-6 * ref
+        assert abs(d[2] - ref) <= (1e-8 if prec == "fp64" else 1e-6) * ref
 
 
 def test_single_node_and_edge():
