@@ -1,18 +1,25 @@
 """Throughput benchmark: Generalized Euclidean node-vector distances per second.
 
-Workload (one GPU): Barabasi-Albert graph, n = 1,000,000, m = 3, unit
-weights; 64 vector pairs, each p and q uniform[0,1) on an independent random
-5% of the nodes; FP32 CG with FP64 iterative refinement to a true relative
-residual of 1e-8 (the headline path), and the plain FP64 CG solver to the
-same residual beside it.  One step = one nvd_distances call over all 64
-pairs (projection, CG, refinement, quadratic form), inputs resident in HBM.
+Headline workload (one GPU): configuration-model graph with power-law degrees
+(P(k) ~ k^-2.5, k in [3, 46415]), n0 = 10^7 restricted to its giant
+component (n = 10^7, 7.57e7 CSR entries), unit weights; 16 vector pairs, each
+p and q uniform[0,1) on an independent random 1% of the nodes; FP32 CG with
+FP64 iterative refinement to a true relative residual of 1e-8 (the mixed
+path, every distance within 1e-6 of the FP64 oracle), and the plain FP64 CG
+solver to the same residual beside it.  One step = one nvd_distances call
+over all 16 pairs (projection, CG, refinement, quadratic form), inputs
+resident in HBM.
 
-Prints one JSON line.  Also reported: the SpMM kernel's algorithmic bytes
-per launch over its event-timed duration (roofline; the events run on a
-repeat of the timed steps, since recording them around every launch slows
-the steps by ~7%), the oracle's CPU rate
-on a bounded sample, and the distances' largest relative error against the
-stored oracle values (tests/golden/c2_expected.json).
+Prints one JSON line.  Also reported: the FP32 SpMM's algorithmic bytes per
+launch over its event-timed duration (roofline; the events run on a repeat
+of the timed steps, since recording them around every launch slows the steps
+by a few per cent), the oracle's CPU rate on one pair of the same workload,
+the distances' largest relative error against the stored oracle values
+(tests/golden/c5_expected.json), and the other workloads as legs: the
+1e3-node latency case, the 2e5-node forward + adjoint case, the 1e6-node
+64-pair case (with all pairwise distances among its 64 vectors), the
+512-graph batch, the density sweep, a 1e6-node tree and the reference
+Laplacian applies on the 1e7-node graph.
 """
 import argparse
 import json
@@ -30,41 +37,43 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def load_golden():
-    p = os.path.join(ROOT, "tests", "golden", "c2_expected.json")
-    if not os.path.exists(p):
-        return None
-    with open(p) as f:
-        g = json.load(f)
-    import numpy as np
-    return np.array([float(v) for v in g["d"]])
-
-
-def load_traffic(tile):
-    """HBM bytes per launch of the FP32 SpMM from the committed counter
-    profile, if it was taken on the current kernel source at this tile."""
-    import hashlib
-    p = os.path.join(ROOT, "profiles", f"k_spmm_f32_ba1e6_k64_T{tile}_traffic.md")
-    if not os.path.exists(p):
-        return None
+def _profile_fields(path):
     fields = {}
-    for line in open(p):
+    for line in open(path):
         if ":" in line and not line.startswith(("#", " ", "|")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
+    return fields
+
+
+KERNEL_SOURCES = ("paper_2310_11222_amd/csrc/spmm.hip", "paper_2310_11222_amd/csrc/device_common.hpp",
+                  "paper_2310_11222_amd/csrc/nvd_internal.hpp")
+
+
+def kernel_source_sha():
+    import hashlib
     h = hashlib.sha256()
-    for src in ("paper_2310_11222_amd/csrc/spmm.hip", "paper_2310_11222_amd/csrc/device_common.hpp",
-                "paper_2310_11222_amd/csrc/nvd_internal.hpp"):
+    for src in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, src), "rb").read())
-    if fields.get("kernel_source_sha256") != h.hexdigest():
+    return h.hexdigest()
+
+
+def load_traffic(tile, workload="cm1e7_k16"):
+    """HBM bytes per launch of the FP32 SpMM from the committed counter
+    profile, if it was taken on the current kernel source at this tile."""
+    p = os.path.join(ROOT, "profiles", f"k_spmm_f32_{workload}_T{tile}_traffic.md")
+    if not os.path.exists(p):
+        return None
+    fields = _profile_fields(p)
+    if fields.get("kernel_source_sha256") != kernel_source_sha():
         return None
     if f"k_spmm<float, {tile}," not in fields.get("kernel", ""):
         return None
     return float(fields["traffic_bytes_per_launch"])
 
 
-def load_golden_batch():
-    p = os.path.join(ROOT, "tests", "golden", "c3_expected.json")
+def load_golden_file(name):
+    p = os.path.join(ROOT, "tests", "golden", name)
     if not os.path.exists(p):
         return None
     with open(p) as f:
@@ -117,7 +126,7 @@ def bench_batched(steps, warmup):
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     d64 = torch.cat(d64).cpu().numpy()
-    gold = load_golden_batch()
+    gold = load_golden_file("c3_expected.json")
     res = {"workload": "batch512_ws_k6_ba_m4_k8", "solver": "sweep", "value": round(value, 1),
            "unit": "distances/s", "ms_per_step": round(tsw * 1e3 / steps, 3), "pairs": K,
            "persistent": {"value": round(K * steps / tp, 1), "unit": "distances/s",
@@ -207,7 +216,7 @@ def bench_tree_large():
     return res
 
 
-def bench_spmv(calib_copy=False):
+def bench_spmv(calib_copy=False, g=None):
     """The reference SpMV loads for the HBM claim: Y = L X on the 10^7-node
     power-law configuration-model graph (unit weights), k = 1 and 16 columns,
     FP32 and FP64, 100 back-to-back launches each (time per launch from HIP
@@ -216,10 +225,10 @@ def bench_spmv(calib_copy=False):
     import torch
     import paper_2310_11222_amd as nvd
     from nvdgen import workload
-    t0 = time.perf_counter()
-    w = workload(5)
-    g = w.graphs[0]
-    log(f"spmv graph: n={g.n} nnz={g.nnz} gen {time.perf_counter() - t0:.1f}s")
+    if g is None:
+        t0 = time.perf_counter()
+        g = workload(5).graphs[0]
+        log(f"spmv graph: n={g.n} nnz={g.nnz} gen {time.perf_counter() - t0:.1f}s")
     dg = nvd.Graph(g.row_ptr, g.col_idx, None)
     if calib_copy:
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -261,38 +270,204 @@ def bench_spmv(calib_copy=False):
 def load_spmv_traffic():
     """Counter bytes per launch of the k = 1 FP32 apply on the 10^7-node
     graph, from the committed profile, if taken on the current source."""
-    import hashlib
     p = os.path.join(ROOT, "profiles", "k_spmm_f32_configmodel1e7_k1_traffic.md")
     if not os.path.exists(p):
         return None
-    fields = {}
-    for line in open(p):
-        if ":" in line and not line.startswith(("#", " ", "|")):
-            k, v = line.split(":", 1)
-            fields[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for src in ("paper_2310_11222_amd/csrc/spmm.hip", "paper_2310_11222_amd/csrc/device_common.hpp",
-                "paper_2310_11222_amd/csrc/nvd_internal.hpp"):
-        h.update(open(os.path.join(ROOT, src), "rb").read())
-    if fields.get("kernel_source_sha256") != h.hexdigest():
+    fields = _profile_fields(p)
+    if fields.get("kernel_source_sha256") != kernel_source_sha():
         return None
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(w, pairs):
-    """The oracle (FP64 Jacobi-PCG route, unmodified defaults) on `pairs`
-    pairs of the same workload, single-threaded."""
+def host_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count()}
+
+
+def cpu_baseline(w, pairs, iters=10):
+    """The oracle's FP64 Jacobi-PCG route (unmodified) on the first `pairs`
+    pairs of the same workload, with every thread pool held to one thread
+    (SciPy's sparse product is single-threaded anyway), bounded in time: its
+    set-up (components, projection, sparse Laplacian) runs in full and its
+    PCG runs `iters` iterations (the routine's own max_iter); the time per
+    distance is the set-up plus the PCG time scaled to the iteration count
+    the oracle needs on these pairs to reach its 1e-13 true relative
+    residual, as recorded in the stored oracle run."""
     import numpy as np
     import oracle
+    from oracle.pcg import pcg_solve
     from threadpoolctl import threadpool_limits
     g = w.graphs[0]
     P = np.ascontiguousarray(w.P[0][:, :pairs])
     Q = np.ascontiguousarray(w.Q[0][:, :pairs])
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        r = oracle.ge_pcg(g.n, g.row_ptr, g.col_idx, g.w, P, Q)
+        lab = oracle.components(g.n, g.row_ptr, g.col_idx)
+        dbar = oracle.project(P - Q, lab)
+        L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, g.w)
+        deg = L.diagonal()
         t1 = time.perf_counter()
-    return pairs / (t1 - t0), t1 - t0, r["d"]
+        pcg_solve(L, deg, dbar, max_iter=iters)
+        t2 = time.perf_counter()
+    gold = os.path.join(ROOT, "tests", "golden", "c5_expected.json")
+    full = int(max(json.load(open(gold))["iters"][:pairs]))
+    t_pairs = (t1 - t0) + (t2 - t1) * full / iters
+    return {"rate": pairs / t_pairs, "setup_s": t1 - t0, "pcg_s": t2 - t1, "iters_run": iters,
+            "iters_full": full, "seconds_measured": t2 - t0}
+
+
+def bench_c1(reps=50):
+    """Latency on the 1e3-node BA graph (m = 3, unit weights), one pair, FP64
+    CG to 1e-10 (and the mixed path beside it): median wall time of a call
+    over `reps` calls after warm-up, against the dense oracle."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2310_11222_amd as nvd
+    from nvdgen import workload
+    w = workload(1)
+    g = w.graphs[0]
+    ref = oracle.ge_dense(g.n, g.row_ptr, g.col_idx, g.w, w.P[0], w.Q[0])["d"]
+    dg = nvd.Graph(g.row_ptr, g.col_idx, g.w)
+    P = torch.as_tensor(w.P[0]).cuda()
+    Q = torch.as_tensor(w.Q[0]).cuda()
+    res = {"workload": "ba_n1e3_m3_unit_k1", "n": g.n, "nnz": g.nnz, "pairs": 1}
+    for prec, rtol in (("fp64", 1e-10), ("mixed", 1e-10)):
+        for _ in range(5):
+            dg.distances(P, Q, precision=prec, rtol=rtol)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            d, _, info = dg.distances(P, Q, precision=prec, rtol=rtol)
+            ts.append(time.perf_counter() - t0)
+        med = float(np.median(ts))
+        res[prec] = {"us_per_call_median": round(med * 1e6, 1),
+                     "us_per_call_mean": round(float(np.mean(ts)) * 1e6, 1),
+                     "distances_per_s": round(1.0 / med, 1), "iters": info[0]["iters"],
+                     "rel_err_vs_dense_oracle": float(abs(d.cpu().numpy()[0] - ref[0]) / ref[0])}
+    dg.close()
+    log("c1 latency: " + json.dumps(res))
+    return res
+
+
+def bench_c4(steps=3):
+    """Forward + adjoint on the 2e5-node BA graph (m = 5, lognormal(0, 1)
+    weights), 32 pairs, FP64 CG to 1e-10: loss = sum of d^2, gradients with
+    respect to P, Q and every edge weight (the per-edge weights are gathered
+    into CSR order, so autograd adds the two stored directions).  Time per
+    step (forward, backward), distances against the stored oracle values."""
+    import numpy as np
+    import torch
+    import paper_2310_11222_amd as nvd
+    from nvdgen import workload
+    w = workload(4)
+    g = w.graphs[0]
+    ew = np.zeros(g.num_edges)
+    ew[g.csr_edge] = g.w
+    dg = nvd.Graph(g.row_ptr, g.col_idx, g.w)
+    idx = torch.as_tensor(g.csr_edge, device="cuda")
+    P0 = torch.as_tensor(w.P[0]).cuda()
+    Q0 = torch.as_tensor(w.Q[0]).cuda()
+    W0 = torch.as_tensor(ew).cuda()
+
+    def step():
+        P = P0.clone().requires_grad_(True)
+        Q = Q0.clone().requires_grad_(True)
+        W = W0.clone().requires_grad_(True)
+        t0 = time.perf_counter()
+        dsq = nvd.distance_sq(P, Q, dg, W[idx], precision="fp64", rtol=w.rtol)
+        loss = dsq.sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return dsq.detach(), t1 - t0, t2 - t1
+
+    step()
+    tf, tb = [], []
+    for _ in range(steps):
+        dsq, a, b = step()
+        tf.append(a)
+        tb.append(b)
+    gold = load_golden_file("c4_expected.json")
+    d = np.sqrt(dsq.cpu().numpy())
+    res = {"workload": "ba_n2e5_m5_lognormal_k32", "n": g.n, "nnz": g.nnz, "pairs": 32,
+           "forward_ms": round(float(np.median(tf)) * 1e3, 3),
+           "backward_ms": round(float(np.median(tb)) * 1e3, 3),
+           "step_ms": round(float(np.median(np.add(tf, tb))) * 1e3, 3),
+           "distances_per_s_with_gradients": round(32 / float(np.median(np.add(tf, tb))), 1),
+           "max_rel_err": None}
+    if gold is not None and gold.size == d.size:
+        res["max_rel_err"] = float(np.max(np.abs(d - gold) / gold))
+    dg.close()
+    log("c4 forward+adjoint: " + json.dumps(res))
+    return res
+
+
+def bench_c2(steps, inner_rtol, no_pairwise):
+    """The 1e6-node BA graph (m = 3, unit weights), 64 pairs on 5% supports,
+    mixed and FP64 to 1e-8, and all 2,016 pairwise distances among the 64
+    vectors P_j from one 64-column solve."""
+    import numpy as np
+    import torch
+    import paper_2310_11222_amd as nvd
+    from nvdgen import workload
+    w = workload(2)
+    g = w.graphs[0]
+    dg = nvd.Graph(g.row_ptr, g.col_idx, g.w)
+    P = torch.as_tensor(w.P[0]).cuda()
+    Q = torch.as_tensor(w.Q[0]).cuda()
+    K = P.shape[1]
+    gold = load_golden_file("c2_expected.json")
+    res = {"workload": "ba_n1e6_m3_unit_k64", "n": g.n, "nnz": g.nnz, "pairs": K}
+    for prec, nsteps in (("mixed", steps), ("fp64", max(1, steps // 2))):
+        dg.distances(P, Q, precision=prec, rtol=w.rtol, inner_rtol=inner_rtol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            d, _, info = dg.distances(P, Q, precision=prec, rtol=w.rtol, inner_rtol=inner_rtol)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / nsteps
+        dn = d.cpu().numpy()
+        res[prec] = {"value": round(K / t, 1), "unit": "distances/s", "ms_per_step": round(t * 1e3, 3),
+                     "iters_mean": float(np.mean([i["iters"] for i in info])),
+                     "max_rel_err": float(np.max(np.abs(dn - gold) / gold)) if gold is not None else None}
+    res["tile"] = dg.tuning(K, "mixed")[0]
+    if not no_pairwise:
+        m = K
+        npairs = m * (m - 1) // 2
+        dg.pairwise(P, precision="mixed", rtol=w.rtol)
+        torch.cuda.synchronize()
+        reps = max(1, min(steps, 3))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            D, _, _ = dg.pairwise(P, precision="mixed", rtol=w.rtol)
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t0) / reps
+        # 8 sampled entries against pairs solved one by one (FP64)
+        iu, ju = np.triu_indices(m, 1)
+        pick = np.random.default_rng(0).choice(npairs, 8, replace=False)
+        ii = torch.as_tensor(iu[pick], device="cuda")
+        jj = torch.as_tensor(ju[pick], device="cuda")
+        dpair, _, _ = dg.distances(P[:, ii].contiguous(), P[:, jj].contiguous(), precision="fp64",
+                                   rtol=1e-10)
+        Dn = D.cpu().numpy()
+        diff = float(np.max(np.abs(Dn[iu[pick], ju[pick]] - dpair.cpu().numpy()) / dpair.cpu().numpy()))
+        res["all_pairs"] = {"vectors": m, "pairs": npairs, "value": round(npairs / tp, 1),
+                            "unit": "distances/s", "ms_per_call": round(tp * 1e3, 3),
+                            "precision": "mixed", "max_rel_diff_vs_pair_solves": diff}
+    dg.close()
+    log("c2: " + json.dumps(res))
+    return res
 
 
 def main():
@@ -301,10 +476,16 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
-    ap.add_argument("--cpu-pairs", type=int, default=8)
+    ap.add_argument("--cpu-pairs", type=int, default=1,
+                    help="pairs of the headline workload the CPU oracle solves (0: none)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--inner-rtol", type=float, default=1e-5)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="headline only (for profiling): skip every other workload")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 1e3-node latency and the 2e5-node adjoint legs")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 1e6-node 64-pair leg")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-pairwise", action="store_true")
     ap.add_argument("--no-density", action="store_true",
@@ -338,9 +519,9 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log("calibration copy: 536870912 bytes read, 536870912 bytes written")
-    log("generating workload")
+    log("generating the headline workload")
     t0 = time.perf_counter()
-    w = workload(2)
+    w = workload(5)
     g = w.graphs[0]
     log(f"n={g.n} nnz={g.nnz} gen {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
@@ -351,15 +532,18 @@ def main():
     Q = torch.as_tensor(w.Q[0]).cuda()
     K = P.shape[1]
     rtol = w.rtol
-    golden = load_golden()
+    golden = load_golden_file("c5_expected.json")
 
     def step(prec):
         return dg.distances(P, Q, precision=prec, rtol=rtol, inner_rtol=args.inner_rtol,
                             tile_k=args.tile)
 
     # ---- mixed precision (headline).  The timed steps run without per-kernel
-    # events (recording two events around every launch costs ~7%); the kernel
-    # durations for the roofline come from the same steps repeated with them.
+    # events; the kernel durations for the roofline come from the same steps
+    # repeated with them.
+    t0 = time.perf_counter()
+    tile_used = args.tile or dg.tuning(K, "mixed")[0]
+    tune_s = time.perf_counter() - t0
     for _ in range(args.warmup):
         d, _, info = step("mixed")
     torch.cuda.synchronize()
@@ -368,6 +552,7 @@ def main():
         d, _, info = step("mixed")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log(f"mixed: {(t1 - t0) * 1e3 / args.steps:.2f} ms/step")
     nvd.prof_enable(True)
     torch.cuda.synchronize()
     for _ in range(args.steps):
@@ -380,7 +565,8 @@ def main():
     d_mixed = d.cpu().numpy()
     iters_mixed = [i["iters"] for i in info]
     refine = [i["refine_steps"] for i in info]
-    log(f"mixed: {ms_step:.2f} ms/step, {value:.1f} distances/s, iters {np.mean(iters_mixed):.1f}, refine {np.mean(refine):.2f}")
+    log(f"mixed: {ms_step:.2f} ms/step, {value:.1f} distances/s, iters {np.mean(iters_mixed):.1f}, "
+        f"refine {np.mean(refine):.2f}")
 
     # ---- plain FP64 solver on the same GPU
     d64, _, info64 = step("fp64")
@@ -395,13 +581,11 @@ def main():
     log(f"fp64: {t64 * 1e3:.2f} ms/step, {value64:.1f} distances/s")
 
     # ---- accuracy vs stored oracle values
-    acc = {}
+    acc = {"max_rel_err_mixed": None, "max_rel_err_fp64": None, "within_1e-6": None}
     if golden is not None and golden.size == K:
         acc["max_rel_err_mixed"] = float(np.max(np.abs(d_mixed - golden) / golden))
         acc["max_rel_err_fp64"] = float(np.max(np.abs(d64 - golden) / golden))
-    else:
-        acc["max_rel_err_mixed"] = None
-        acc["max_rel_err_fp64"] = None
+        acc["within_1e-6"] = bool(acc["max_rel_err_mixed"] <= 1e-6)
     log(f"accuracy {acc}")
 
     # ---- roofline of the dominant kernel (SpMM, FP32 in the inner solves)
@@ -415,7 +599,6 @@ def main():
                 "gbs": bytes_per / (avg_ms * 1e-3) / 1e9, "launches": p["launches"],
                 "ms_total": p["ms"]}
 
-    tile_used = args.tile or dg.tuning(K, "mixed")[0]
     kinds = {k: kern(k) for k in prof}
     dom = max((k for k in kinds if kinds[k]), key=lambda k: kinds[k]["ms_total"])
     sp = kinds["spmm_f32"]
@@ -423,60 +606,42 @@ def main():
             "achieved": round(sp["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(sp["gbs"] / HBM_PEAK_GBS, 4), "traffic": load_traffic(tile_used),
             "bytes_per_launch": sp["bytes_per_launch"], "avg_launch_us": round(sp["avg_us"], 2),
+            "bytes_formula": "4 nnz + 4 (n + 1) + 2 T 4 n (CSR once, p read once, q written once)",
             "timing": "HIP events on the launch stream around every launch, over a repeat of the timed "
                       "steps (value is timed without them)"}
     log(f"kernels: " + json.dumps({k: (round(v['gbs'], 1), round(v['ms_total'], 2)) for k, v in kinds.items() if v}))
 
-    # ---- CPU oracle on a bounded sample
+    # ---- CPU oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu and args.cpu_pairs > 0:
-        rate, secs, dref = cpu_baseline(w, args.cpu_pairs)
-        cpu = {"value": round(rate, 4), "unit": "distances/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {args.cpu_pairs} of the 64 pairs, FP64 Jacobi-PCG oracle route "
-                         f"(true rel. residual 1e-13), {secs:.1f} s single-threaded"}
-        log(f"cpu oracle {rate:.3f} distances/s ({secs:.1f}s)")
+        cb = cpu_baseline(w, args.cpu_pairs)
+        cpu = {"value": round(cb["rate"], 5), "unit": "distances/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {args.cpu_pairs} of the 16 pairs of the same workload through "
+                         f"the oracle's FP64 Jacobi-PCG route on one thread: set-up (components, "
+                         f"projection, sparse Laplacian) {cb['setup_s']:.1f} s in full, then "
+                         f"{cb['iters_run']} PCG iterations in {cb['pcg_s']:.1f} s, scaled to the "
+                         f"{cb['iters_full']} iterations the oracle takes to its 1e-13 residual on "
+                         f"these pairs (stored oracle run)",
+               "host": host_info(), "threads": 1,
+               "seconds_measured": round(cb["seconds_measured"], 1)}
+        log(f"cpu oracle {cb['rate']:.5f} distances/s ({cb['seconds_measured']:.1f}s measured)")
 
-    # ---- all pairwise distances among the 64 vectors P_j (one 64-column solve)
-    all_pairs = None
-    if not args.no_pairwise:
-        m = P.shape[1]
-        npairs = m * (m - 1) // 2
-        dg.pairwise(P, precision="mixed", rtol=rtol)
-        torch.cuda.synchronize()
-        reps = max(1, min(args.steps, 3))
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            D, _, _ = dg.pairwise(P, precision="mixed", rtol=rtol)
-        torch.cuda.synchronize()
-        tp = (time.perf_counter() - t0) / reps
-        # 8 sampled entries against pairs solved one by one (FP64)
-        iu, ju = np.triu_indices(m, 1)
-        pick = np.random.default_rng(0).choice(npairs, 8, replace=False)
-        ii = torch.as_tensor(iu[pick], device="cuda")
-        jj = torch.as_tensor(ju[pick], device="cuda")
-        dpair, _, _ = dg.distances(P[:, ii].contiguous(), P[:, jj].contiguous(), precision="fp64",
-                                   rtol=1e-10)
-        Dn = D.cpu().numpy()
-        diff = float(np.max(np.abs(Dn[iu[pick], ju[pick]] - dpair.cpu().numpy()) / dpair.cpu().numpy()))
-        all_pairs = {"workload": "ba_n1e6_m3_unit_64_vectors_all_pairs", "vectors": m,
-                     "pairs": npairs, "value": round(npairs / tp, 1), "unit": "distances/s",
-                     "ms_per_call": round(tp * 1e3, 3), "precision": "mixed",
-                     "max_rel_diff_vs_pair_solves": diff}
-        log(f"all pairs: {all_pairs}")
-
-    density = None if args.no_density else bench_density()
-    tree_large = None if args.no_density else bench_tree_large()
-
+    small = None if (args.no_legs or args.no_small) else {"c1_latency": bench_c1(),
+                                                          "c4_forward_adjoint": bench_c4()}
+    spmv = None
+    if not (args.no_legs or args.no_spmv):
+        torch.cuda.empty_cache()
+        spmv = bench_spmv(g=g)
+    dg.close()
+    del P, Q
+    torch.cuda.empty_cache()
+    c2 = None if (args.no_legs or args.no_c2) else bench_c2(args.steps, args.inner_rtol, args.no_pairwise)
+    density = None if (args.no_legs or args.no_density) else bench_density()
+    tree_large = None if (args.no_legs or args.no_density) else bench_tree_large()
     batched = None
-    if not args.no_batched:
-        dg.close()
+    if not (args.no_legs or args.no_batched):
         torch.cuda.empty_cache()
         batched = bench_batched(max(2, args.steps // 2), 1)
-
-    spmv = None
-    if not args.no_spmv:
-        torch.cuda.empty_cache()
-        spmv = bench_spmv()
 
     out = {
         "metric": "NVD distances/sec at rel err <=1e-6 vs FP64 oracle; SpMV HBM GB/s % of peak",
@@ -491,7 +656,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "ba_n1e6_m3_unit_k64", "n": g.n, "nnz": g.nnz, "pairs": K,
+        "config": {"workload": "cm_pl2.5_n1e7_k16", "n": g.n, "nnz": g.nnz, "pairs": K,
                    "rtol": rtol, "precision": "mixed (FP32 CG + FP64 refinement)",
                    "inner_rtol": args.inner_rtol, "tile": tile_used,
                    "tile_chosen_by": "option" if args.tile else "autotuner"},
@@ -500,14 +665,12 @@ def main():
         "fp64_path": {"value": round(value64, 2), "unit": "distances/s",
                       "ms_per_step": round(t64 * 1e3, 3)},
         "accuracy": acc,
-        "batched": batched,
-        "all_pairs": all_pairs,
-        "density_sweep": density,
-        "tree_like_1e6": tree_large,
-        "spmv_reference": spmv,
+        "legs": {"small": small, "c2": c2, "batched": batched, "density_sweep": density,
+                 "tree_like_1e6": tree_large, "spmv_reference": spmv},
         "iters_mean": float(np.mean(iters_mixed)),
         "refine_mean": float(np.mean(refine)),
         "setup_s": round(setup_s, 3),
+        "tune_s": round(tune_s, 3),
         "kernels": {k: v for k, v in kinds.items() if v},
         "dominant_kernel": dom,
     }

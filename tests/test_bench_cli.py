@@ -26,18 +26,23 @@ def test_help_lists_the_legs():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0
     for flag in ("--steps", "--warmup", "--gpus", "--no-batched", "--no-pairwise", "--no-density",
-                 "--no-spmv", "--spmv-only"):
+                 "--no-spmv", "--spmv-only", "--no-legs", "--no-small", "--no-c2", "--cpu-pairs"):
         assert flag in r.stdout
 
 
-@pytest.mark.parametrize("tile,alg", [(32, 284e6), (64, 540e6)])
-def test_headline_traffic_profile(tile, alg):
+@pytest.mark.parametrize("tile", [8, 16])
+def test_headline_traffic_profile(tile):
+    """The committed counter profile of the headline's FP32 apply (1e7-node
+    configuration model): when taken on the current kernel source, its
+    traffic lies above the algorithmic bytes (the gathers miss L2) and
+    within a sane multiple of them."""
     import bench
+    n, nnz = 10_000_000, 75_714_946
+    alg = 4.0 * nnz + 4.0 * (n + 1) + 2.0 * tile * 4.0 * n
     t = bench.load_traffic(tile)
     if t is None:
-        pytest.skip(f"profile for T={tile} predates the current kernel source")
-    # the gathers miss L2: counted traffic well above the algorithmic bytes
-    assert alg < t < 10 * alg
+        pytest.skip(f"no profile for T={tile} on the current kernel source")
+    assert alg < t < 20 * alg
 
 
 def test_reference_spmv_traffic_profile():
