@@ -150,8 +150,9 @@ def bench_density():
     """Section 4.2 density sweep: |V| = 10^4, average degree 1..64 on ER, BA,
     WS and SBM, 8 pairs per graph, mixed precision to 1e-8 (the time of one
     call after a warm-up call, and the largest CG iteration count), with the
-    Jacobi diagonal and with the spanning-tree preconditioner (section 3.2;
-    the forest is built by the warm-up call)."""
+    Jacobi diagonal, the spanning-tree preconditioner and the
+    approximate-Cholesky factor (section 3.2; the forest and the factor are
+    built by the warm-up call, whose time is not counted)."""
     import torch
     import paper_2310_11222_amd as nvd
     from nvdgen import density_graph, DENSITY_MODELS, DENSITY_DEGREES
@@ -164,7 +165,7 @@ def bench_density():
             Pd = torch.as_tensor(P).cuda()
             Qd = torch.as_tensor(Q).cuda()
             row = {"avg_degree": d, "components": dg.stats()["n_comp"]}
-            for pre, key in (("jacobi", ""), ("tree", "tree_")):
+            for pre, key in (("jacobi", ""), ("tree", "tree_"), ("achol", "achol_")):
                 dg.distances(Pd, Qd, precision="mixed", rtol=1e-8, precond=pre)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -174,11 +175,15 @@ def bench_density():
                 row[key + "ms_per_8"] = round(t * 1e3, 3)
                 row[key + "converged"] = all(i["status"] == 0 for i in info)
                 row[key + "iters"] = max(i["iters"] for i in info)
+            st = dg.stats()
+            row["achol_rounds"] = st["achol_rounds"]
+            row["achol_remainder"] = st["achol_remainder"]
             rows.append(row)
             dg.close()
         out[model] = rows
-    log("density sweep (ms per 8 distances, jacobi / tree): " +
-        json.dumps({m: [(r["ms_per_8"], r["tree_ms_per_8"]) for r in v] for m, v in out.items()}))
+    log("density sweep (ms per 8 distances, jacobi / tree / achol): " +
+        json.dumps({m: [(r["ms_per_8"], r["tree_ms_per_8"], r["achol_ms_per_8"]) for r in v]
+                    for m, v in out.items()}))
     return {"workload": "density_sweep_n1e4_deg1_to_64", "models": out}
 
 
@@ -442,6 +447,22 @@ def bench_c2(steps, inner_rtol, no_pairwise):
                      "iters_mean": float(np.mean([i["iters"] for i in info])),
                      "max_rel_err": float(np.max(np.abs(dn - gold) / gold)) if gold is not None else None}
     res["tile"] = dg.tuning(K, "mixed")[0]
+    # the approximate-Cholesky preconditioner on the same graph and pairs
+    t0 = time.perf_counter()
+    dg.distances(P[:, :1], Q[:, :1], precision="mixed", rtol=w.rtol, precond="achol")
+    torch.cuda.synchronize()
+    t_fac = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    d, _, info = dg.distances(P, Q, precision="mixed", rtol=w.rtol, precond="achol")
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    st = dg.stats()
+    dn = d.cpu().numpy()
+    res["mixed_achol"] = {"value": round(K / t, 1), "unit": "distances/s", "ms_per_step": round(t * 1e3, 3),
+                          "iters_mean": float(np.mean([i["iters"] for i in info])),
+                          "factor_and_first_call_s": round(t_fac, 3), "rounds": st["achol_rounds"],
+                          "factor_nnz": st["achol_factor_nnz"], "remainder": st["achol_remainder"],
+                          "max_rel_err": float(np.max(np.abs(dn - gold) / gold)) if gold is not None else None}
     if not no_pairwise:
         m = K
         npairs = m * (m - 1) // 2

@@ -103,9 +103,20 @@ enum {
                                many iterations plus one in exact arithmetic),
                                else the Jacobi diagonal.  Batches always use
                                the Jacobi diagonal under this flag. */
-  NVD_OUT_DSQ = 16u         /* nvd_distances: d_out receives d^2 (the
+  NVD_OUT_DSQ = 16u,        /* nvd_distances: d_out receives d^2 (the
                                quadratic form, clamped at 0) instead of d */
+  NVD_PRECOND_ACHOL = 32u   /* nvd_distances / nvd_pairwise: precondition CG
+                               with an approximate Cholesky factor of L
+                               (section 3.2: sparse approximate Gaussian
+                               elimination, cliques replaced by sampled
+                               edges; the solver of Table 2), built on the
+                               host on first use and applied as two
+                               triangular solves of one GPU step per
+                               elimination round.  Excludes NVD_PRECOND_TREE
+                               and NVD_PRECOND_AUTO.  Not for batches. */
 };
+/* nvd_pair_info.flags */
+enum { NVD_INFO_FP64_FALLBACK = 1 };
 /* nvd_graph_create_ex flags: where the CSR arrays live */
 enum { NVD_PTR_HOST = 0u, NVD_PTR_DEVICE = 1u };
 
@@ -127,7 +138,7 @@ typedef struct nvd_opts {
   int32_t tile_k;      /* columns per SpMM pass: 1,2,4,8,16,32,64; 0 = the
                           library's autotuned choice */
   uint32_t flags;      /* NVD_WARM_START, NVD_BATCH_PERSISTENT, NVD_PRECOND_TREE,
-                          NVD_PRECOND_AUTO, NVD_OUT_DSQ */
+                          NVD_PRECOND_AUTO, NVD_OUT_DSQ, NVD_PRECOND_ACHOL */
 } nvd_opts;
 
 typedef struct nvd_pair_info {
@@ -135,7 +146,10 @@ typedef struct nvd_pair_info {
                            (NVD_E_DEVICE: the persistent batch launch failed) */
   int32_t iters;        /* CG iterations (all inner solves summed) */
   int32_t refine_steps; /* MIXED outer steps (0 for FP64) */
-  int32_t reserved;
+  int32_t flags;        /* NVD_INFO_FP64_FALLBACK: the mixed solve stalled
+                           (FP32 could not reduce the FP64 residual by 2x in
+                           two consecutive outer steps) and the pair was
+                           finished by the FP64 solver from its current x */
   double rel_res;       /* final true ||delta_bar - L x|| / ||delta_bar|| */
   double dsq_plain;     /* delta_bar^T x */
   double dsq;           /* delta_bar^T x + x^T r (returned d = sqrt(max(dsq,0))) */
@@ -151,6 +165,12 @@ typedef struct nvd_stats {
   int64_t device_bytes; /* device memory held by the handle (workspace incl.) */
   int32_t weighted;     /* 1 if explicit weights were given */
   int32_t self_loops_dropped; /* number of diagonal entries removed on input */
+  int64_t achol_rounds; /* approximate-Cholesky factor (0s until built):
+                           elimination rounds = steps of each triangular
+                           solve */
+  int64_t achol_factor_nnz;  /* off-diagonal entries of the factor */
+  int64_t achol_remainder;   /* vertices left to the Schur diagonal after
+                                the last round */
 } nvd_stats;
 
 /* ---- library ----------------------------------------------------------- */

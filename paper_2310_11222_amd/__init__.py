@@ -107,8 +107,10 @@ def opts(precision="fp64", rtol=1e-10, inner_rtol=1e-5, max_iter=20000, max_refi
         o.flags |= _abi.NVD_PRECOND_TREE
     elif precond == "auto":
         o.flags |= _abi.NVD_PRECOND_AUTO
+    elif precond == "achol":
+        o.flags |= _abi.NVD_PRECOND_ACHOL
     elif precond != "jacobi":
-        raise ValueError("precond must be 'jacobi', 'tree' or 'auto'")
+        raise ValueError("precond must be 'jacobi', 'tree', 'auto' or 'achol'")
     return o
 
 
@@ -224,8 +226,8 @@ class Graph:
                   precond="jacobi", out="d"):
         """Returns (d, X or None, info list).  P, Q: (n, k) or (n,) float64.
         precond: "jacobi" (the diagonal), "tree" (a spanning forest, solved
-        exactly) or "auto" (the forest when at most n/100 edges lie off it,
-        else the diagonal).  X0: starting guess, (n, k) like P.
+        exactly), "auto" (the forest when at most n/100 edges lie off it,
+        else the diagonal) or "achol" (an approximate Cholesky factor).  X0: starting guess, (n, k) like P.
         out: "d" for distances, "dsq" for their squares."""
         torch = _torch()
         P = _as_dev64(P, "P")

@@ -17,6 +17,8 @@ NVD_BATCH_PERSISTENT = 2
 NVD_PRECOND_TREE = 4
 NVD_PRECOND_AUTO = 8
 NVD_OUT_DSQ = 16
+NVD_PRECOND_ACHOL = 32
+NVD_INFO_FP64_FALLBACK = 1
 NVD_PTR_HOST, NVD_PTR_DEVICE = 0, 1
 
 
@@ -28,7 +30,7 @@ class NvdOpts(C.Structure):
 
 class PairInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("refine_steps", C.c_int32),
-                ("reserved", C.c_int32), ("rel_res", C.c_double), ("dsq_plain", C.c_double),
+                ("flags", C.c_int32), ("rel_res", C.c_double), ("dsq_plain", C.c_double),
                 ("dsq", C.c_double)]
 
 
@@ -36,7 +38,8 @@ class Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("n_comp", C.c_int64),
                 ("n_isolated", C.c_int64), ("max_deg", C.c_int64), ("n_long_rows", C.c_int64),
                 ("device_bytes", C.c_int64), ("weighted", C.c_int32),
-                ("self_loops_dropped", C.c_int32)]
+                ("self_loops_dropped", C.c_int32), ("achol_rounds", C.c_int64),
+                ("achol_factor_nnz", C.c_int64), ("achol_remainder", C.c_int64)]
 
 
 _P = C.c_void_p

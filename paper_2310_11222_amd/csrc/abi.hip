@@ -129,6 +129,10 @@ nvd_status check_solve_opts(const nvd_opts* o) {
     set_error("nvd_opts: rtol and inner_rtol must lie in (0, 1)");
     return NVD_E_ARG;
   }
+  if ((o->flags & NVD_PRECOND_ACHOL) && (o->flags & (NVD_PRECOND_TREE | NVD_PRECOND_AUTO))) {
+    set_error("nvd_opts: NVD_PRECOND_ACHOL excludes NVD_PRECOND_TREE and NVD_PRECOND_AUTO");
+    return NVD_E_ARG;
+  }
   if (o->max_iter < 1 || o->max_refine < 1) {
     set_error("nvd_opts: max_iter and max_refine must be >= 1");
     return NVD_E_ARG;
@@ -250,6 +254,9 @@ nvd_status nvd_graph_stats(const nvd_graph* h, nvd_stats* s) {
   s->device_bytes = g->bytes;
   s->weighted = g->weighted ? 1 : 0;
   s->self_loops_dropped = g->self_loops;
+  s->achol_rounds = g->achol ? g->achol->rounds : 0;
+  s->achol_factor_nnz = g->achol ? g->achol->nnz : 0;
+  s->achol_remainder = g->achol ? g->achol->remainder : 0;
   return NVD_OK;
 }
 
@@ -339,7 +346,8 @@ nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double*
   sp.max_iter = o.max_iter;
   sp.max_refine = o.max_refine;
   sp.warm = (o.flags & NVD_WARM_START) != 0;
-  sp.tree = use_tree(g, o.flags);
+  sp.achol = (o.flags & NVD_PRECOND_ACHOL) != 0;
+  sp.tree = sp.achol || use_tree(g, o.flags);
   sp.out_dsq = (o.flags & NVD_OUT_DSQ) != 0;
   int tile = o.tile_k;
   if (tile == 0) tile = choose_tile(g, k, o.precision, s);
@@ -428,6 +436,9 @@ nvd_status nvd_graph_set_weights(nvd_graph* h, const double* w, void* stream) {
   // built from the host copy of the weights: refresh the copy, drop the forest
   free_tree(g->tree);
   g->tree = nullptr;
+  if (g->achol) g->bytes -= g->achol->bytes;
+  free_achol(g->achol);
+  g->achol = nullptr;
   g->h_w.resize(std::max(g->nnz, 1));
   if (hipMemcpy(g->h_w.data(), g->w64, sizeof(double) * g->nnz, hipMemcpyDeviceToHost) != hipSuccess) {
     set_error("nvd_graph_set_weights: copying the weights back failed");

@@ -1,0 +1,471 @@
+// Approximate-Cholesky preconditioner: sparse approximate Gaussian
+// elimination of the Laplacian (section 3.2: Cholesky elimination made sparse
+// by sampling the cliques it would create; the solver behind Table 2),
+// applied as the preconditioner of CG.
+//
+// Factorization (host, once per graph and weights).  Eliminating a vertex v
+// with neighbours u_i (weights w_i, W = sum w_i) writes the factor column
+// c_i = w_i / W and the pivot W, and exact elimination would join every pair
+// of neighbours with weight w_i w_j / W (a clique).  Instead the neighbours
+// are taken in ascending weight order and each u_i except the last is joined
+// to ONE later neighbour u_j, drawn with probability w_j / S_i (S_i the sum
+// of the later weights), with weight w_i S_i / W.  The expected weight of
+// each pair is the clique's w_i w_j / W, at most deg - 1 edges are added for
+// the deg removed, and degree-1 and degree-2 eliminations are exact (a leaf
+// adds nothing; a degree-2 vertex joins its two neighbours with the series
+// weight w_1 w_2 / W).  Draws come from a counter-based hash of (vertex,
+// neighbour rank), so a graph always gets the same factor.
+//
+// Order, for the GPU.  Vertices are eliminated in rounds: each round takes a
+// maximal set of live vertices no two of which are adjacent, greedily in
+// ascending current degree.  Eliminations within a round commute (none
+// touches another's neighbourhood), so the triangular solves process a
+// round in parallel: the depth of each solve is the number of rounds.
+// Elimination preserves connectivity, and the last vertex of each component
+// ends with no neighbours: its pivot is 0 (the Laplacian's null space) and it
+// grounds its component.  After kAcholMaxRounds rounds the vertices still
+// live (if any) keep the diagonal of their current Schur complement (Jacobi
+// on the remainder).
+//
+// Application z = M^-1 r, M = F D F^T (F unit lower triangular by
+// elimination order), per column of the tile:
+//   r <- r - mean_C(r)  (per component; see below)
+//   forward, rounds in order:  y_u = r_u + sum over eliminated v with u in
+//                              v's column: c_vu y_v
+//   backward, remainder first, then rounds in reverse:
+//                              z_v = y_v / W_v + sum_{u in v's column} c_vu z_u
+// (y is kept in z.)  The map with ground pivots 0 is a grounded inverse, whose
+// image of a constant vector is large on long, thin graphs; the rounding-level
+// component mean that the solver's residual carries would then swamp z, so
+// it is removed first.  z then differs from the exact pseudoinverse image
+// by a constant per component, which does not change r^T z and which the
+// solver's projections remove.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <numeric>
+#include <vector>
+
+#include "device_common.hpp"
+
+namespace nvd {
+
+constexpr int kAcholMaxRounds = 256;   // default cap on elimination rounds
+constexpr uint64_t kAcholSeed = 0x2310112200000001ull;
+
+namespace {
+
+uint64_t mix64(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
+}
+
+// Uniform [0, 1) from (vertex, neighbour rank): a counter-based hash.
+double draw(uint64_t v, uint64_t i) {
+  const uint64_t h = mix64(kAcholSeed ^ mix64(v * 0x9e3779b97f4a7c15ull + i));
+  return (double)(h >> 11) * 0x1.0p-53;
+}
+
+struct Nb {
+  int u;
+  double w;
+};
+
+struct HostFactor {
+  std::vector<int> order;          // vertices by position (rounds, then remainder)
+  std::vector<int> round_off;      // positions: round r is [round_off[r], round_off[r+1]); last range: remainder
+  std::vector<int> col_off;        // [n+1] by position: the factor column of order[p]
+  std::vector<int> col_idx;        // later vertex
+  std::vector<double> col_c;       // coefficient w / W
+  std::vector<double> inv_pivot;   // by position: 1 / W (0: ground), remainder: 1 / Schur diagonal
+  int rounds = 0;
+  int grounds = 0;
+  int remainder = 0;
+};
+
+// Merge repeated neighbours (sum of weights) and drop dead ones.
+void compact(std::vector<Nb>& a, const std::vector<char>& alive) {
+  size_t k = 0;
+  for (size_t i = 0; i < a.size(); ++i)
+    if (alive[a[i].u]) a[k++] = a[i];
+  a.resize(k);
+  if (k < 2) return;
+  std::sort(a.begin(), a.end(), [](const Nb& x, const Nb& y) { return x.u < y.u; });
+  size_t o = 0;
+  for (size_t i = 1; i < a.size(); ++i) {
+    if (a[i].u == a[o].u)
+      a[o].w += a[i].w;
+    else
+      a[++o] = a[i];
+  }
+  a.resize(o + 1);
+}
+
+HostFactor factor_graph(const DevGraph* g, int max_rounds) {
+  const int n = g->n;
+  const std::vector<int>& rp = g->h_rp;
+  const std::vector<int>& ci = g->h_ci;
+  const bool weighted = !g->h_w.empty();
+  std::vector<std::vector<Nb>> adj(n);
+  for (int v = 0; v < n; ++v) {
+    adj[v].reserve(rp[v + 1] - rp[v]);
+    for (int e = rp[v]; e < rp[v + 1]; ++e) adj[v].push_back(Nb{ci[e], weighted ? g->h_w[e] : 1.0});
+  }
+  std::vector<char> alive(n, 1), blocked(n, 0);
+  std::vector<int> live(n);
+  std::iota(live.begin(), live.end(), 0);
+  HostFactor f;
+  f.order.reserve(n);
+  f.col_off.reserve(n + 1);
+  f.col_off.push_back(0);
+  f.inv_pivot.reserve(n);
+  f.round_off.push_back(0);
+  std::vector<int> cand, next_live, bucket_cnt;
+  std::vector<double> pre;
+  for (int r = 0; r < max_rounds && !live.empty(); ++r) {
+    // current degrees (merged, live neighbours only), candidates in
+    // ascending degree, ties by a hash of (vertex, round)
+    int dmax = 0;
+    for (int v : live) {
+      compact(adj[v], alive);
+      dmax = std::max(dmax, (int)adj[v].size());
+    }
+    bucket_cnt.assign(dmax + 2, 0);
+    for (int v : live) ++bucket_cnt[adj[v].size() + 1];
+    for (int d = 0; d <= dmax; ++d) bucket_cnt[d + 1] += bucket_cnt[d];
+    cand.resize(live.size());
+    for (int v : live) cand[bucket_cnt[adj[v].size()]++] = v;
+    // (within a degree bucket, vertices stay in increasing id order)
+    // greedy maximal independent set
+    next_live.clear();
+    const int round_begin = (int)f.order.size();
+    for (int v : cand) {
+      if (blocked[v]) continue;
+      f.order.push_back(v);
+      blocked[v] = 1;
+      for (const Nb& nb : adj[v]) blocked[nb.u] = 1;
+    }
+    const int round_end = (int)f.order.size();
+    // eliminate the round's vertices
+    for (int p = round_begin; p < round_end; ++p) {
+      const int v = f.order[p];
+      std::vector<Nb>& a = adj[v];
+      const int d = (int)a.size();
+      double W = 0.0;
+      for (const Nb& nb : a) W += nb.w;
+      if (d == 0 || !(W > 0.0)) {
+        f.inv_pivot.push_back(0.0);   // last vertex of its component: the ground
+        ++f.grounds;
+      } else {
+        f.inv_pivot.push_back(1.0 / W);
+      }
+      for (const Nb& nb : a) {
+        f.col_idx.push_back(nb.u);
+        f.col_c.push_back(nb.w / W);
+      }
+      f.col_off.push_back((int)f.col_idx.size());
+      if (d >= 2) {
+        std::stable_sort(a.begin(), a.end(), [](const Nb& x, const Nb& y) { return x.w < y.w; });
+        pre.assign(d + 1, 0.0);
+        for (int i = 0; i < d; ++i) pre[i + 1] = pre[i] + a[i].w;
+        for (int i = 0; i + 1 < d; ++i) {
+          const double S = pre[d] - pre[i + 1];            // weights after i
+          const double t = pre[i + 1] + draw((uint64_t)v, (uint64_t)i) * S;
+          // the later neighbour j whose cumulative range holds t
+          int j = (int)(std::upper_bound(pre.begin() + i + 2, pre.begin() + d + 1, t) - pre.begin()) - 1;
+          if (j <= i) j = i + 1;
+          if (j >= d) j = d - 1;
+          const double wn = a[i].w * S / W;
+          adj[a[i].u].push_back(Nb{a[j].u, wn});
+          adj[a[j].u].push_back(Nb{a[i].u, wn});
+        }
+      }
+      alive[v] = 0;
+      std::vector<Nb>().swap(a);
+    }
+    for (int p = round_begin; p < round_end; ++p) blocked[f.order[p]] = 0;
+    for (int v : live) {
+      if (alive[v]) {
+        blocked[v] = 0;
+        next_live.push_back(v);
+      }
+    }
+    live.swap(next_live);
+    f.round_off.push_back((int)f.order.size());
+    f.rounds = r + 1;
+  }
+  // remainder: the diagonal of the current Schur complement
+  for (int v : live) {
+    compact(adj[v], alive);
+    double s = 0.0;
+    for (const Nb& nb : adj[v]) s += nb.w;
+    f.order.push_back(v);
+    f.inv_pivot.push_back(s > 0.0 ? 1.0 / s : 0.0);
+    f.col_off.push_back((int)f.col_idx.size());
+    ++f.remainder;
+  }
+  f.round_off.push_back((int)f.order.size());
+  return f;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+// Per-component column means of r.  One component: block partial sums over
+// fixed row ranges, then one block adds them in order (k_am_total).  Several
+// components: one block per component over its node list.
+constexpr int kAmBlocks = 256;
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_am_part(int n, int T, const V* __restrict__ r,
+                                                 double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int t = threadIdx.x;
+  const int c = t % T;
+  const int rpb = 256 / T;
+  const long rows = ((long)n + gridDim.x - 1) / gridDim.x;
+  const long lo = (long)blockIdx.x * rows;
+  const long hi = min((long)n, lo + rows);
+  double acc = 0.0;
+  for (long i = lo + t / T; i < hi; i += rpb) acc += (double)r[i * T + c];
+  sh[t] = acc;
+  __syncthreads();
+  for (int h = 128; h >= T; h >>= 1) {
+    if (t < h) sh[t] += sh[t + h];
+    __syncthreads();
+  }
+  if (t < T) part[(long)blockIdx.x * kMaxTile + t] = sh[t];
+}
+
+__global__ void k_am_total(int n, int T, int nb, const double* __restrict__ part, double* __restrict__ mean) {
+  const int t = threadIdx.x;
+  if (t >= T) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[(long)b * kMaxTile + t];
+  mean[t] = s / (double)n;
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_am_comp(int ncomp, int T, const int* __restrict__ perm,
+                                                 const int* __restrict__ off, const V* __restrict__ r,
+                                                 double* __restrict__ mean) {
+  __shared__ double sh[256];
+  const int t = threadIdx.x;
+  const int c = t % T;
+  const int rpb = 256 / T;
+  for (int k = blockIdx.x; k < ncomp; k += gridDim.x) {
+    const int lo = off[k], hi = off[k + 1];
+    double acc = 0.0;
+    for (int p = lo + t / T; p < hi; p += rpb) acc += (double)r[(long)perm[p] * T + c];
+    sh[t] = acc;
+    __syncthreads();
+    for (int h = 128; h >= T; h >>= 1) {
+      if (t < h) sh[t] += sh[t + h];
+      __syncthreads();
+    }
+    if (t < T) mean[(long)k * kMaxTile + t] = sh[t] / (double)(hi - lo);
+    __syncthreads();
+  }
+}
+
+// Forward round: positions [p0, p1); y (kept in z) of each vertex from r,
+// minus its component mean, plus the pulls from earlier vertices.  T lanes
+// per vertex.
+template <typename V, typename C>
+__global__ __launch_bounds__(256) void k_am_fwd(int p0, int p1, int T, const int* __restrict__ order,
+                                                const int* __restrict__ in_off,
+                                                const int* __restrict__ in_idx,
+                                                const C* __restrict__ in_c, const V* __restrict__ r,
+                                                const int* __restrict__ comp,
+                                                const double* __restrict__ mean, V* __restrict__ z) {
+  const int vpb = 256 / T;
+  const int p = p0 + blockIdx.x * vpb + threadIdx.x / T;
+  const int c = threadIdx.x % T;
+  if (p >= p1) return;
+  const int u = order[p];
+  double acc = (double)r[(long)u * T + c] - mean[(long)comp[u] * kMaxTile + c];
+  for (int e = in_off[p]; e < in_off[p + 1]; ++e)
+    acc += (double)in_c[e] * (double)z[(long)in_idx[e] * T + c];
+  z[(long)u * T + c] = (V)acc;
+}
+
+// Backward round: positions [p0, p1); z_v = y_v / W_v + pulls from later
+// vertices (final already).
+template <typename V, typename C>
+__global__ __launch_bounds__(256) void k_am_bwd(int p0, int p1, int T, const int* __restrict__ order,
+                                                const int* __restrict__ out_off,
+                                                const int* __restrict__ out_idx,
+                                                const C* __restrict__ out_c,
+                                                const C* __restrict__ inv_pivot, V* __restrict__ z) {
+  const int vpb = 256 / T;
+  const int p = p0 + blockIdx.x * vpb + threadIdx.x / T;
+  const int c = threadIdx.x % T;
+  if (p >= p1) return;
+  const int v = order[p];
+  double acc = (double)z[(long)v * T + c] * (double)inv_pivot[p];
+  for (int e = out_off[p]; e < out_off[p + 1]; ++e)
+    acc += (double)out_c[e] * (double)z[(long)out_idx[e] * T + c];
+  z[(long)v * T + c] = (V)acc;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+void free_achol(AcholPre* ap) {
+  if (!ap) return;
+  void* ptrs[] = {ap->order,  ap->out_off, ap->out_idx, ap->out_c64, ap->out_c32, ap->in_off,
+                  ap->in_idx, ap->in_c64,  ap->in_c32,  ap->ip64,    ap->ip32,    ap->mean,
+                  ap->part};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete ap;
+}
+
+static int achol_max_rounds() {
+  if (const char* e = std::getenv("NVD_ACHOL_ROUNDS")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 0 && v <= 1000000) return (int)v;
+  }
+  return kAcholMaxRounds;
+}
+
+nvd_status ensure_achol(DevGraph* g) {
+  if (g->achol) return NVD_OK;
+  const int n = g->n;
+  HostFactor f = factor_graph(g, achol_max_rounds());
+  // forward pull lists: for position q (vertex order[q]) the entries (v, c)
+  // of the earlier columns that name it
+  std::vector<int> pos_of(n);
+  for (int p = 0; p < n; ++p) pos_of[f.order[p]] = p;
+  const size_t nf = f.col_idx.size();
+  if (nf >= (size_t)INT32_MAX) {
+    set_error("approximate Cholesky: factor beyond 2^31 entries");
+    return NVD_E_UNSUPPORTED;
+  }
+  std::vector<int> in_off(n + 1, 0);
+  for (size_t e = 0; e < nf; ++e) ++in_off[pos_of[f.col_idx[e]] + 1];
+  for (int p = 0; p < n; ++p) in_off[p + 1] += in_off[p];
+  std::vector<int> in_idx(nf), fill(in_off.begin(), in_off.end() - 1);
+  std::vector<double> in_c(nf);
+  for (int p = 0; p < n; ++p) {
+    const int v = f.order[p];
+    for (int e = f.col_off[p]; e < f.col_off[p + 1]; ++e) {
+      const int q = pos_of[f.col_idx[e]];
+      in_idx[fill[q]] = v;
+      in_c[fill[q]] = f.col_c[e];
+      ++fill[q];
+    }
+  }
+  std::vector<float> col_c32(f.col_c.begin(), f.col_c.end()), in_c32(in_c.begin(), in_c.end());
+  std::vector<float> ip32(f.inv_pivot.begin(), f.inv_pivot.end());
+  AcholPre* ap = new AcholPre();
+  ap->rounds = f.rounds;
+  ap->grounds = f.grounds;
+  ap->remainder = f.remainder;
+  ap->nnz = (int64_t)nf;
+  ap->round_off = f.round_off;
+  nvd_status st = NVD_OK;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (st != NVD_OK) return;
+    if (hipMalloc(p, std::max<size_t>(bytes, 4)) != hipSuccess) {
+      set_error("approximate Cholesky: device allocation failed");
+      st = NVD_E_NOMEM;
+    } else {
+      ap->bytes += (int64_t)bytes;
+    }
+  };
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (st != NVD_OK || bytes == 0) return;
+    if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("approximate Cholesky: upload failed");
+      st = NVD_E_DEVICE;
+    }
+  };
+  alloc((void**)&ap->order, sizeof(int) * n);
+  alloc((void**)&ap->out_off, sizeof(int) * (n + 1));
+  alloc((void**)&ap->out_idx, sizeof(int) * nf);
+  alloc((void**)&ap->out_c64, sizeof(double) * nf);
+  alloc((void**)&ap->out_c32, sizeof(float) * nf);
+  alloc((void**)&ap->in_off, sizeof(int) * (n + 1));
+  alloc((void**)&ap->in_idx, sizeof(int) * nf);
+  alloc((void**)&ap->in_c64, sizeof(double) * nf);
+  alloc((void**)&ap->in_c32, sizeof(float) * nf);
+  alloc((void**)&ap->ip64, sizeof(double) * n);
+  alloc((void**)&ap->ip32, sizeof(float) * n);
+  alloc((void**)&ap->mean, sizeof(double) * (size_t)std::max(g->n_comp, 1) * kMaxTile);
+  alloc((void**)&ap->part, sizeof(double) * kAmBlocks * kMaxTile);
+  up(ap->order, f.order.data(), sizeof(int) * n);
+  up(ap->out_off, f.col_off.data(), sizeof(int) * (n + 1));
+  up(ap->out_idx, f.col_idx.data(), sizeof(int) * nf);
+  up(ap->out_c64, f.col_c.data(), sizeof(double) * nf);
+  up(ap->out_c32, col_c32.data(), sizeof(float) * nf);
+  up(ap->in_off, in_off.data(), sizeof(int) * (n + 1));
+  up(ap->in_idx, in_idx.data(), sizeof(int) * nf);
+  up(ap->in_c64, in_c.data(), sizeof(double) * nf);
+  up(ap->in_c32, in_c32.data(), sizeof(float) * nf);
+  up(ap->ip64, f.inv_pivot.data(), sizeof(double) * n);
+  up(ap->ip32, ip32.data(), sizeof(float) * n);
+  if (st != NVD_OK) {
+    free_achol(ap);
+    return st;
+  }
+  g->achol = ap;
+  g->bytes += ap->bytes;
+  return NVD_OK;
+}
+
+template <typename V>
+static nvd_status achol_solve_t(DevGraph* g, int T, const V* r, V* z, hipStream_t s) {
+  AcholPre* ap = g->achol;
+  const int n = g->n;
+  // component means of r
+  if (g->n_comp == 1) {
+    k_am_part<V><<<kAmBlocks, 256, 0, s>>>(n, T, r, ap->part);
+    k_am_total<<<1, 64, 0, s>>>(n, T, kAmBlocks, ap->part, ap->mean);
+  } else {
+    k_am_comp<V><<<std::min(g->n_comp, 4096), 256, 0, s>>>(g->n_comp, T, g->comp_perm, g->comp_off, r,
+                                                           ap->mean);
+  }
+  const int vpb = 256 / T;
+  const int nr = (int)ap->round_off.size() - 1;   // rounds, then the remainder
+  using C = V;
+  const C* in_c = sizeof(V) == 8 ? (const C*)ap->in_c64 : (const C*)ap->in_c32;
+  const C* out_c = sizeof(V) == 8 ? (const C*)ap->out_c64 : (const C*)ap->out_c32;
+  const C* ip = sizeof(V) == 8 ? (const C*)ap->ip64 : (const C*)ap->ip32;
+  for (int k = 0; k < nr; ++k) {
+    const int p0 = ap->round_off[k], p1 = ap->round_off[k + 1];
+    if (p1 <= p0) continue;
+    k_am_fwd<V, C><<<(p1 - p0 + vpb - 1) / vpb, 256, 0, s>>>(p0, p1, T, ap->order, ap->in_off,
+                                                             ap->in_idx, in_c, r, g->comp, ap->mean, z);
+  }
+  for (int k = nr - 1; k >= 0; --k) {
+    const int p0 = ap->round_off[k], p1 = ap->round_off[k + 1];
+    if (p1 <= p0) continue;
+    k_am_bwd<V, C><<<(p1 - p0 + vpb - 1) / vpb, 256, 0, s>>>(p0, p1, T, ap->order, ap->out_off,
+                                                             ap->out_idx, out_c, ip, z);
+  }
+  NVD_HIP(hipGetLastError());
+  return NVD_OK;
+}
+
+nvd_status achol_solve(DevGraph* g, int prec, int T, const void* r, void* z, hipStream_t s) {
+  if (!g->achol) {
+    set_error("approximate Cholesky preconditioner: not set up");
+    return NVD_E_DEVICE;
+  }
+  if (T < 1 || T > kMaxTile || (T & (T - 1))) {
+    set_error("approximate Cholesky preconditioner: tile must be a power of two up to 64");
+    return NVD_E_ARG;
+  }
+  return prec == 0 ? achol_solve_t<double>(g, T, static_cast<const double*>(r), static_cast<double*>(z), s)
+                   : achol_solve_t<float>(g, T, static_cast<const float*>(r), static_cast<float*>(z), s);
+}
+
+}  // namespace nvd

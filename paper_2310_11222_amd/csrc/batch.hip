@@ -749,7 +749,7 @@ __device__ __noinline__ void solve_graph(const BatchArgs& a, int gi, Team& tm, c
     pi.status = team_failed(tm) ? (int)NVD_E_DEVICE : L.stat[t];
     pi.iters = L.it[t];
     pi.refine_steps = L.ref[t];
-    pi.reserved = 0;
+    pi.flags = 0;
     pi.rel_res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
     pi.dsq_plain = bb > 0.0 ? bx : 0.0;
     pi.dsq = dsq;
@@ -1282,7 +1282,7 @@ extern "C" nvd_status nvd_batch_distances(nvd_batch* b, const int32_t* k_per_gra
     set_error("nvd_batch_distances: bad precision");
     return NVD_E_ARG;
   }
-  if (o.flags & NVD_PRECOND_TREE) {
+  if (o.flags & (NVD_PRECOND_TREE | NVD_PRECOND_ACHOL)) {
     set_error("nvd_batch_distances: the tree preconditioner is not available for batches");
     return NVD_E_UNSUPPORTED;
   }

@@ -196,7 +196,7 @@ __device__ __forceinline__ void write_pair(const SArgs& a, const SGraph& sg, int
   pi.status = a.s.stat[i];
   pi.iters = a.s.it[i];
   pi.refine_steps = a.s.ref[i];
-  pi.reserved = 0;
+  pi.flags = 0;
   pi.rel_res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
   pi.dsq_plain = bb > 0.0 ? bx : 0.0;
   pi.dsq = dsq;

@@ -20,11 +20,14 @@
 //           FP32 CG solve of L c = r to inner_rtol; x += c in FP64.
 // Both return d^2 = delta_bar^T x + x^T r from the final FP64 residual.
 #include <algorithm>
+#include <cstddef>
+#include <cstdlib>
 #include <cmath>
 #include <vector>
 
 #include "device_common.hpp"
 #include "prof.hpp"
+#include "refine_guard.hpp"
 
 namespace nvd {
 
@@ -151,6 +154,9 @@ __global__ __launch_bounds__(kBS) void k_proj_init(int n, long cap, ProjSrc src,
     cs->refine[t] = 0;
     cs->status[t] = kStOk;
     cs->itol2[t] = 0.0;
+    cs->stall[t] = 0;
+    cs->fb[t] = 0;
+    cs->fbdone[t] = 0;
   }
   if (t == 0) cs->xseq = cs->xdone = 0;   // a CG run starts: no x update pending
   recount_active(cs, T);
@@ -422,7 +428,8 @@ __global__ __launch_bounds__(kBS) void k_inner_init_any(int T, int n, long cap, 
                                                         MeanSrc m, const float* invd32, float* x32,
                                                         float* r32, float* p32, float* q32,
                                                         double rtol2, double irtol2, int max_refine,
-                                                        int first, ColState* cs, GridRed red) {
+                                                        int first, double stall_ratio2, ColState* cs,
+                                                        GridRed red) {
   constexpr int NE = 4;
   __shared__ double sh[3 * kBS * NE];
   __shared__ double vals[3 * kMaxTile];
@@ -469,11 +476,17 @@ __global__ __launch_bounds__(kBS) void k_inner_init_any(int T, int n, long cap, 
   __syncthreads();
   if (!grid_reduce<kBS>(vals, 3 * T, red)) return;
   if (t < T) {
+    const double rr_old = cs->orr[t];
     cs->orr[t] = vals[t];
     int act = 0;
+    if (cs->oactive[t] && !first)
+      cs->stall[t] = refine_stall_count(rr_old, vals[t], cs->stall[t], stall_ratio2);
     if (cs->oactive[t]) {
       if (!first && vals[t] <= rtol2 * cs->obnorm2[t]) {
         cs->oactive[t] = 0;
+      } else if (refine_hand_to_fp64(cs->stall[t])) {
+        cs->oactive[t] = 0;   // FP32 no longer reduces the residual: FP64 from here
+        cs->fb[t] = 1;
       } else if (cs->refine[t] >= max_refine) {
         cs->oactive[t] = 0;
         cs->status[t] = kStNoconv;
@@ -605,6 +618,30 @@ __global__ void k_outer_check(int T, int n, double rtol2, int max_refine, ColSta
   recount_active(cs, T);
 }
 
+// After an inner FP32 solve: a pair whose solve ran out of iterations
+// (status NOCONV from the inner CG; k_accum kept its last good x) is handed
+// to the FP64 solver instead of being closed, like a stalled one.
+__global__ void k_inner_failed_to_fp64(int T, int max_iter, ColState* cs) {
+  const int t = threadIdx.x;
+  if (t < T && cs->status[t] == kStNoconv && cs->it_cur[t] >= max_iter) {
+    cs->status[t] = kStOk;
+    cs->fb[t] = 1;
+  }
+  recount_active(cs, T);
+}
+
+// Open the pairs handed to the FP64 solver (and only those): the FP64 CG
+// restarts from the true residual r = delta_bar - L x of their current x.
+__global__ void k_fp64_open(int T, ColState* cs) {
+  const int t = threadIdx.x;
+  if (t < T) {
+    cs->oactive[t] = cs->fb[t];
+    if (cs->fb[t]) cs->fbdone[t] = 1;
+    cs->fb[t] = 0;
+  }
+  recount_active(cs, T);
+}
+
 // d^2 = delta_bar^T x + x^T r from the last residual pass; d = sqrt(max(d^2, 0)).
 // shift_n > 0: that pass saw x before its mean was removed (connected graph
 // of shift_n nodes).  Shifting x by -m (m = sum x / n) leaves r unchanged
@@ -634,7 +671,7 @@ __global__ void k_finish(int T, int mark_open_noconv, ColState* cs, double* d_ou
   pi.status = st;
   pi.iters = cs->iters[t];
   pi.refine_steps = cs->refine[t];
-  pi.reserved = 0;
+  pi.flags = cs->fbdone[t] ? NVD_INFO_FP64_FALLBACK : 0;
   pi.rel_res = rel;
   pi.dsq_plain = bb > 0.0 ? bx : 0.0;
   pi.dsq = dsq;
@@ -709,9 +746,11 @@ static int reduce_grid(long cap) {
 static size_t padded_cap(int n, int T) { return (((size_t)n * T + 15) / 16) * 16; }
 
 struct PollWords {
-  int n_active, n_oactive, it_max, pad;
+  int n_active, n_oactive, it_max, n_fb;
   double worst;
 };
+static_assert(offsetof(ColState, worst) - offsetof(ColState, n_active) == offsetof(PollWords, worst),
+              "the polled words must be laid out as in ColState");
 
 static nvd_status poll(Workspace* ws, hipStream_t s, int* n_active, int* n_oactive,
                        PollWords* all = nullptr) {
@@ -725,13 +764,21 @@ static nvd_status poll(Workspace* ws, hipStream_t s, int* n_active, int* n_oacti
   return NVD_OK;
 }
 
-// CG iterations until no column of the tile is active.
-// Start of a tree-preconditioned CG run on r: p = z = L_T^+ r, rho = r^T z.
+// The explicit preconditioner solve z = M^-1 r: the spanning forest's
+// L_T^+, or the approximate-Cholesky factor's (F D F^T)^-1.
+static nvd_status z_solve(DevGraph* g, const SolveParams& sp, int prec, int T, const void* r, void* z,
+                          hipStream_t s) {
+  return sp.achol ? achol_solve(g, prec, T, r, z, s) : tree_solve(g, prec, T, r, z, s);
+}
+
+// Start of a CG run with an explicit preconditioner solve on r: p = z =
+// M^-1 r, rho = r^T z.
 template <typename V>
-static nvd_status tree_start(DevGraph* g, Workspace* ws, int T, const V* r, V* p, hipStream_t s) {
+static nvd_status tree_start(DevGraph* g, Workspace* ws, int T, const V* r, V* p,
+                             const SolveParams& sp, hipStream_t s) {
   const long cap = (long)padded_cap(g->n, T);
   const int rgrid = reduce_grid(cap / Vec16<V>::N);
-  NVD_TRY(tree_solve(g, sizeof(V) == 8 ? 0 : 1, T, r, p, s));
+  NVD_TRY(z_solve(g, sp, sizeof(V) == 8 ? 0 : 1, T, r, p, s));
   NVD_TILE_SWITCH(T, (k_rz<V, TT, 0><<<rgrid, kBS, 0, s>>>(cap, r, p, ws->cs, ws->red)));
   NVD_HIP(hipGetLastError());
   return NVD_OK;
@@ -787,8 +834,8 @@ static nvd_status cg_loop(DevGraph* g, Workspace* ws, int T, V* x, V* r, V* p, V
       ids.push_back(pid);
       pid = prof_begin(s, sizeof(V) == 8 ? PK_DIR64 : PK_DIR32, dir_bytes);
       if (sp.tree) {
-        // z = L_T^+ r into q (free until the next apply), then beta and p
-        NVD_TRY(tree_solve(g, sizeof(V) == 8 ? 0 : 1, T, r, q, s));
+        // z = M^-1 r into q (free until the next apply), then beta and p
+        NVD_TRY(z_solve(g, sp, sizeof(V) == 8 ? 0 : 1, T, r, q, s));
         NVD_TILE_SWITCH(T, (k_rz<V, TT, 1><<<rgrid, kBS, 0, s>>>(cap, r, q, ws->cs, ws->red)));
         NVD_TILE_SWITCH(T, (k_direction_z<V, TT><<<sgrid, kBS, 0, s>>>(cap, x, p, q, ws->cs)));
       } else {
@@ -963,14 +1010,25 @@ nvd_status project_tile(DevGraph* g, int T, const double* P, const double* Q, in
   return NVD_OK;
 }
 
-// Solve pairs [c0, c0+T) of the caller's P, Q.
+// Solve pairs [c0, c0+T) of the caller's P, Q, in the graph's cached
+// workspace (allocated or grown here).
 nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
                       const SolveParams& sp, double* d_out, double* X, int64_t ldx,
                       nvd_pair_info* info_dev, hipStream_t s) {
+  NVD_TRY(ensure_workspace(g, T, sp.precision == NVD_MIXED));
+  if (sp.achol)
+    NVD_TRY(ensure_achol(g));
+  else if (sp.tree)
+    NVD_TRY(ensure_tree(g, T));
+  return solve_tile_ws(g, g->ws, T, P, Q, ld, sp, d_out, X, ldx, info_dev, s);
+}
+
+// The same in a given workspace, which must hold tile T (and the FP32
+// vectors in mixed precision); allocates nothing.
+nvd_status solve_tile_ws(DevGraph* g, Workspace* ws, int T, const double* P, const double* Q,
+                         int64_t ld, const SolveParams& sp, double* d_out, double* X,
+                         int64_t ldx, nvd_pair_info* info_dev, hipStream_t s) {
   const bool mixed = sp.precision == NVD_MIXED;
-  NVD_TRY(ensure_workspace(g, T, mixed));
-  if (sp.tree) NVD_TRY(ensure_tree(g, T));
-  Workspace* ws = g->ws;
   const int n = g->n;
   const long cap = (long)padded_cap(n, T);
   const int grid = stream_grid(cap);
@@ -983,7 +1041,7 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
                          n, cap, ProjSrc{P, ld, Q, ld}, m, g->invd64, ws->b64, ws->x64, ws->r64,
                          ws->p64, ws->q64, mixed ? 0 : 1, ws->cs, ws->red)));
   NVD_HIP(hipGetLastError());
-  if (sp.tree && !mixed) NVD_TRY(tree_start<double>(g, ws, T, ws->r64, ws->p64, s));
+  if (sp.tree && !mixed) NVD_TRY(tree_start<double>(g, ws, T, ws->r64, ws->p64, sp, s));
 
   SpmmCall resid{};
   resid.g = g;
@@ -1007,16 +1065,10 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
     have_x = true;
   }
 
-  int shift_n = 0;   // > 0: x's mean is removed after the last residual pass
-  if (!mixed) {
-    if (have_x) {
-      // r = delta_bar - L x0, then CG from there
-      NVD_TRY(launch_spmm(resid, ws->red, s));
-      NVD_TILE_SWITCH(T, (k_restart<TT><<<grid, kBS, 0, s>>>(n, cap, ws->r64, ws->p64, ws->q64,
-                                                             g->invd64, ws->cs, ws->red)));
-      NVD_HIP(hipGetLastError());
-      if (sp.tree) NVD_TRY(tree_start<double>(g, ws, T, ws->r64, ws->p64, s));
-    }
+  // FP64 CG from the restart state set up by the caller (k_restart, or
+  // k_proj_init), then the true residual, with up to two restarts from it;
+  // ends with x mean-zero and a residual pass of the final x.
+  auto fp64_cg = [&]() -> nvd_status {
     int restarts = 0;
     for (;;) {
       NVD_TRY(cg_loop<double>(g, ws, T, ws->x64, ws->r64, ws->p64, ws->q64, g->invd64, rtol2,
@@ -1035,13 +1087,38 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
       NVD_TILE_SWITCH(T, (k_restart<TT><<<grid, kBS, 0, s>>>(n, cap, ws->r64, ws->p64, ws->q64,
                                                              g->invd64, ws->cs, ws->red)));
       NVD_HIP(hipGetLastError());
-      if (sp.tree) NVD_TRY(tree_start<double>(g, ws, T, ws->r64, ws->p64, s));
+      if (sp.tree) NVD_TRY(tree_start<double>(g, ws, T, ws->r64, ws->p64, sp, s));
     }
+    return NVD_OK;
+  };
+
+  int shift_n = 0;   // > 0: x's mean is removed after the last residual pass
+  bool fp64_finish = !mixed;   // the FP64 solver ran last (open pairs are NOCONV)
+  if (!mixed) {
+    if (have_x) {
+      // r = delta_bar - L x0, then CG from there
+      NVD_TRY(launch_spmm(resid, ws->red, s));
+      NVD_TILE_SWITCH(T, (k_restart<TT><<<grid, kBS, 0, s>>>(n, cap, ws->r64, ws->p64, ws->q64,
+                                                             g->invd64, ws->cs, ws->red)));
+      NVD_HIP(hipGetLastError());
+      if (sp.tree) NVD_TRY(tree_start<double>(g, ws, T, ws->r64, ws->p64, sp, s));
+    }
+    NVD_TRY(fp64_cg());
   } else {
     const double irtol2 = sp.inner_rtol * sp.inner_rtol;
+    // NVD_REFINE_STALL_RATIO2 (in [0, 1]) replaces the stagnation rule's
+    // ratio: 0 treats every outer step as stalled, which makes the hand-over
+    // to the FP64 solver testable on any graph
+    double stall_ratio2 = kStallRatio2;
+    if (const char* e = std::getenv("NVD_REFINE_STALL_RATIO2")) {
+      const double v = std::strtod(e, nullptr);
+      if (v >= 0.0 && v <= 1.0) stall_ratio2 = v;
+    }
     const bool connected = g->n_comp == 1;
     bool first = !have_x;
     bool resid_current = false;   // the last residual pass saw the current x
+    PollWords pw{};               // the loop leaves by a break right after a poll
+    bool polled = false;
     for (int step = 0; step <= sp.max_refine; ++step) {
       MeanSrc mr{};
       const double* src = ws->b64;
@@ -1054,9 +1131,11 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
           mr.dots_sum = ws->cs->dots[3];
           k_outer_check<<<1, 64, 0, s>>>(T, n, rtol2, sp.max_refine, ws->cs);
           NVD_HIP(hipGetLastError());
-          int no = 0;
-          NVD_TRY(poll(ws, s, nullptr, &no));
-          if (no == 0) break;
+          NVD_TRY(poll(ws, s, nullptr, nullptr, &pw));
+          if (pw.n_oactive == 0) {
+            polled = true;
+            break;
+          }
         } else {
           NVD_TRY(mean_into(g, ws, T, ProjSrc{ws->r64, T, nullptr, 0}, &mr, s));
         }
@@ -1064,13 +1143,15 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
       }
       k_inner_init_any<<<grid, kBS, 0, s>>>(T, n, cap, src, mr, g->invd32, ws->x32, ws->r32,
                                             ws->p32, ws->q32, rtol2, irtol2, sp.max_refine,
-                                            first ? 1 : 0, ws->cs, ws->red);
+                                            first ? 1 : 0, stall_ratio2, ws->cs, ws->red);
       NVD_HIP(hipGetLastError());
-      if (sp.tree) NVD_TRY(tree_start<float>(g, ws, T, ws->r32, ws->p32, s));
+      if (sp.tree) NVD_TRY(tree_start<float>(g, ws, T, ws->r32, ws->p32, sp, s));
       if (first || !connected) {
-        int no = 0;
-        NVD_TRY(poll(ws, s, nullptr, &no));
-        if (no == 0) break;
+        NVD_TRY(poll(ws, s, nullptr, nullptr, &pw));
+        if (pw.n_oactive == 0) {
+          polled = true;
+          break;
+        }
       }
       first = false;
       // (an inner set-up that closed every pair leaves nothing active: the
@@ -1078,10 +1159,24 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
       NVD_TRY(cg_loop<float>(g, ws, T, ws->x32, ws->r32, ws->p32, ws->q32, g->invd32, irtol2,
                              sp.max_iter, sp, s));
       NVD_TILE_SWITCH(T, (k_accum<TT><<<grid, kBS, 0, s>>>(cap, ws->x64, ws->x32, ws->cs)));
+      k_inner_failed_to_fp64<<<1, 64, 0, s>>>(T, sp.max_iter, ws->cs);
       NVD_HIP(hipGetLastError());
       resid_current = false;
     }
-    if (connected && resid_current) {
+    // pairs on which FP32 stalled (or ran out of inner iterations) are
+    // finished by the FP64 solver, from their current x (the count comes
+    // with the poll that ended the loop, else a poll of its own)
+    if (!polled) NVD_TRY(poll(ws, s, nullptr, nullptr, &pw));
+    if (pw.n_fb > 0) {
+      NVD_TRY(launch_spmm(resid, ws->red, s));
+      k_fp64_open<<<1, 64, 0, s>>>(T, ws->cs);
+      NVD_TILE_SWITCH(T, (k_restart<TT><<<grid, kBS, 0, s>>>(n, cap, ws->r64, ws->p64, ws->q64,
+                                                             g->invd64, ws->cs, ws->red)));
+      NVD_HIP(hipGetLastError());
+      if (sp.tree) NVD_TRY(tree_start<double>(g, ws, T, ws->r64, ws->p64, sp, s));
+      NVD_TRY(fp64_cg());
+      fp64_finish = true;
+    } else if (connected && resid_current) {
       // the last residual pass is that of the final x: its dots give the
       // distance once x's mean is accounted for (k_finish); x itself is
       // shifted only where it is returned
@@ -1100,7 +1195,8 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
     if (shift_n > 0) xm.dots_sum = ws->cs->dots[4];
     NVD_TILE_SWITCH(T, (k_xfinal<TT><<<grid, kBS, 0, s>>>(n, ws->x64, xm, X, ldx)));
   }
-  k_finish<<<1, 64, 0, s>>>(T, mixed ? 0 : 1, ws->cs, d_out, info_dev, shift_n, sp.out_dsq ? 1 : 0);
+  k_finish<<<1, 64, 0, s>>>(T, fp64_finish ? 1 : 0, ws->cs, d_out, info_dev, shift_n,
+                            sp.out_dsq ? 1 : 0);
   NVD_HIP(hipGetLastError());
   return NVD_OK;
 }

@@ -140,15 +140,17 @@ __device__ bool grid_reduce(double* vals, int ndt, const GridRed& red) {
 __device__ __forceinline__ void recount_active(ColState* cs, int T) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    int a = 0, o = 0, im = 0;
+    int a = 0, o = 0, im = 0, f = 0;
     for (int c = 0; c < T; ++c) {
       a += cs->active[c];
       o += cs->oactive[c];
+      f += cs->fb[c];
       im = cs->it_cur[c] > im ? cs->it_cur[c] : im;
     }
     cs->n_active = a;
     cs->n_oactive = o;
     cs->it_max = im;
+    cs->n_fb = f;
   }
 }
 

@@ -525,6 +525,7 @@ nvd_status graph_destroy(DevGraph* g) {
   (void)hipDeviceSynchronize();
   if (g->ws) free_workspace(g->ws);
   free_tree(g->tree);
+  free_achol(g->achol);
   free_graph_arrays(g);
   delete g;
   return NVD_OK;

@@ -53,10 +53,13 @@ struct ColState {
   int it_cur[kMaxTile];     // iterations of the running CG
   int status[kMaxTile];
   int refine[kMaxTile];
-  int n_active;             // count of active[] (host polls these four words)
+  int stall[kMaxTile];      // mixed: consecutive outer steps that stalled
+  int fb[kMaxTile];         // mixed: handed to the FP64 solver, not yet run
+  int fbdone[kMaxTile];     // mixed: finished by the FP64 solver (info flag)
+  int n_active;             // count of active[] (host polls these five words)
   int n_oactive;
   int it_max;               // largest it_cur[] over the tile
-  int pad;
+  int n_fb;                 // count of fb[]
   double worst;             // largest rr / (rtol^2 bnorm2) over active columns
   // x += alpha p is applied by the direction kernel, for the iteration whose
   // update kernel ran: that kernel's last block advances xseq, and an update
@@ -106,6 +109,32 @@ struct TreePre {
   int n_tree_edges = 0;
 };
 
+// Approximate-Cholesky factor for its preconditioner (built on first use):
+// vertices by elimination position, the factor's columns (pull lists for the
+// backward solve) and their transpose (pull lists for the forward solve),
+// 1 / pivot by position, and scratch for the component means of r.
+struct AcholPre {
+  int* order = nullptr;        // [n] vertex at each position (rounds, then remainder)
+  int* out_off = nullptr;      // [n+1] by position
+  int* out_idx = nullptr;      // [nnz] later vertex
+  double* out_c64 = nullptr;   // [nnz] coefficient w / W
+  float* out_c32 = nullptr;
+  int* in_off = nullptr;       // [n+1] by position
+  int* in_idx = nullptr;       // [nnz] earlier vertex
+  double* in_c64 = nullptr;
+  float* in_c32 = nullptr;
+  double* ip64 = nullptr;      // [n] by position: 1 / pivot (0: ground)
+  float* ip32 = nullptr;
+  double* mean = nullptr;      // [n_comp][kMaxTile]
+  double* part = nullptr;      // [blocks][kMaxTile]
+  std::vector<int> round_off;  // host: positions of each round, last range = remainder
+  int rounds = 0;
+  int grounds = 0;
+  int remainder = 0;
+  int64_t nnz = 0;
+  int64_t bytes = 0;
+};
+
 struct DevGraph {
   int n = 0;
   int nnz = 0;                 // internal nnz (self-loops removed)
@@ -139,6 +168,7 @@ struct DevGraph {
   int tuned_tile[2][8] = {};   // [precision][log2 k bucket] -> tile (0 = not tuned)
   int tuned_nl[2][8] = {};     // [precision][log2 tile] -> neighbour lanes (0 = default)
   TreePre* tree = nullptr;     // spanning forest, built when first needed
+  AcholPre* achol = nullptr;   // approximate-Cholesky factor, built when first needed
 };
 
 struct Workspace {
@@ -212,12 +242,20 @@ struct SolveParams {
   int nl;                   // SpMM lanes per row across neighbours (0 = default)
   int grid;                 // SpMM short-row grid (0 = default)
   bool warm;
-  bool tree;                // spanning-tree preconditioner instead of Jacobi
+  bool tree;                // an explicit preconditioner solve z = M^-1 r instead of
+                            // Jacobi: the spanning forest, or (achol) the factor
+  bool achol;               // the approximate-Cholesky factor
   bool out_dsq;             // d_out receives d^2 instead of d
 };
 nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
                       const SolveParams& sp, double* d_out, double* X, int64_t ldx,
                       nvd_pair_info* info_dev, hipStream_t s);
+nvd_status solve_tile_ws(DevGraph* g, Workspace* ws, int T, const double* P, const double* Q,
+                         int64_t ld, const SolveParams& sp, double* d_out, double* X,
+                         int64_t ldx, nvd_pair_info* info_dev, hipStream_t s);
+// Tile for k pairs without timing anything: the autotuner's cached choice,
+// else the fixed heuristic.
+int untimed_tile(const DevGraph* g, int k, int precision);
 nvd_status project_tile(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
                         double* Dbar, int64_t ldd, double* norms, hipStream_t s);
 // Tree preconditioner (tree.hip): set up for tiles up to T; z = L_T^+ r.
@@ -227,6 +265,10 @@ bool use_tree(const DevGraph* g, uint32_t flags);
 nvd_status ensure_tree(DevGraph* g, int T);
 nvd_status tree_solve(DevGraph* g, int prec, int T, const void* r, void* z, hipStream_t s);
 void free_tree(TreePre* tp);
+// Approximate-Cholesky preconditioner (achol.hip): NVD_PRECOND_ACHOL.
+nvd_status ensure_achol(DevGraph* g);
+nvd_status achol_solve(DevGraph* g, int prec, int T, const void* r, void* z, hipStream_t s);
+void free_achol(AcholPre* ap);
 
 // Validation of solver options (NVD_E_ARG with a message).
 nvd_status check_solve_opts(const nvd_opts* o);

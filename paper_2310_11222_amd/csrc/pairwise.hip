@@ -267,7 +267,8 @@ extern "C" nvd_status nvd_pairwise(nvd_graph* h, int32_t m, const double* V, int
   sp.max_iter = o.max_iter;
   sp.max_refine = o.max_refine;
   sp.warm = false;
-  sp.tree = use_tree(g, o.flags);
+  sp.achol = (o.flags & NVD_PRECOND_ACHOL) != 0;
+  sp.tree = sp.achol || use_tree(g, o.flags);
   int tile = o.tile_k;
   if (tile == 0) tile = choose_tile(g, m, o.precision, s);
   std::vector<nvd_pair_info> hinfo(m);

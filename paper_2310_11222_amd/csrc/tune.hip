@@ -71,6 +71,13 @@ int tuned_nl(const DevGraph* g, int precision, int T) {
   return nl > 0 ? nl : default_nl(T);
 }
 
+int untimed_tile(const DevGraph* g, int k, int precision) {
+  if (k <= 8 || g->n < 4096) return heuristic_tile(k);
+  const int p = precision == NVD_MIXED ? 1 : 0;
+  const int t = g->tuned_tile[p][std::min(log2i(k), 7)];
+  return t > 0 ? t : heuristic_tile(k);
+}
+
 int choose_tile(DevGraph* g, int k, int precision, hipStream_t s) {
   if (k <= 8 || g->n < 4096 || tuning_disabled()) return heuristic_tile(k);
   const int p = precision == NVD_MIXED ? 1 : 0;
