@@ -237,6 +237,28 @@ nvd_status nvd_distances(nvd_graph* g, int32_t k, const double* P,
                          double* d_out, double* X_inout, int64_t ldx,
                          nvd_pair_info* info, void* stream);
 
+/* ---- distances without device allocation ---------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of nvd_distances (same arguments, same kernels, same results up to the
+ * order of floating-point sums), with every device buffer beyond the
+ * caller's inputs and outputs taken from one fixed array of 64 MiB that the
+ * library holds on each GPU it runs on until the process ends.  The call
+ * allocates nothing, on the device or in pinned host memory.
+ * Limits: the solve of the widest tile T must fit the array, about
+ *   56 n T bytes (mixed; 40 n T in FP64) + 6.5 MiB + 512 n_comp bytes,
+ * so n T up to about 1e6 (NVD_E_UNSUPPORTED beyond, with the size in the
+ * message); only the Jacobi preconditioner (NVD_PRECOND_TREE, AUTO and ACHOL
+ * give NVD_E_UNSUPPORTED); the tile is opts->tile_k, else the autotuner's cached
+ * choice for this graph, else a fixed heuristic (nothing is timed).
+ * The array keeps the last call's contents; each call clears what must
+ * start at zero.  Calls that overlap on one GPU (two streams or threads)
+ * race on the array: serialise them.  Synchronous, as nvd_distances. */
+nvd_status nvd_distances_noalloc(nvd_graph* g, int32_t k, const double* P,
+                                 const double* Q, int64_t ld, const nvd_opts* opts,
+                                 double* d_out, double* X_inout, int64_t ldx,
+                                 nvd_pair_info* info, void* stream);
+
 /* ---- all pairwise distances among m node vectors --------------------------
  * D[i][j] = d(v_i, v_j) (section 3.1 distance) for the m columns of V, from
  * ONE solve with m right-hand sides: X = L^+ V_bar (section 3.2 solve, the

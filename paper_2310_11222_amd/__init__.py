@@ -223,12 +223,14 @@ class Graph:
     # -- distances ----------------------------------------------------------
     def distances(self, P, Q, precision="fp64", rtol=1e-10, inner_rtol=1e-5, max_iter=20000,
                   max_refine=30, tile_k=0, return_x=False, X0=None, raise_on_noconv=False,
-                  precond="jacobi", out="d"):
+                  precond="jacobi", out="d", noalloc=False):
         """Returns (d, X or None, info list).  P, Q: (n, k) or (n,) float64.
         precond: "jacobi" (the diagonal), "tree" (a spanning forest, solved
         exactly), "auto" (the forest when at most n/100 edges lie off it,
         else the diagonal) or "achol" (an approximate Cholesky factor).  X0: starting guess, (n, k) like P.
-        out: "d" for distances, "dsq" for their squares."""
+        out: "d" for distances, "dsq" for their squares.
+        noalloc: solve through nvd_distances_noalloc (no device allocation by
+        the library; Jacobi only, n * tile up to about 1e6)."""
         torch = _torch()
         P = _as_dev64(P, "P")
         Q = _as_dev64(Q, "Q")
@@ -250,9 +252,9 @@ class Graph:
         elif return_x:
             X = torch.empty_like(P)
         info = (PairInfo * k)()
-        st = load().nvd_distances(self._h, k, _ptr(P), _ptr(Q), P.stride(0), C.byref(o),
-                                  _ptr(d), _ptr(X), X.stride(0) if X is not None else 0,
-                                  info, _stream())
+        fn = load().nvd_distances_noalloc if noalloc else load().nvd_distances
+        st = fn(self._h, k, _ptr(P), _ptr(Q), P.stride(0), C.byref(o), _ptr(d), _ptr(X),
+                X.stride(0) if X is not None else 0, info, _stream())
         if st not in (_abi.NVD_OK, _abi.NVD_E_NOCONV, _abi.NVD_E_BREAKDOWN) or \
                 (raise_on_noconv and st != _abi.NVD_OK):
             check(st, "nvd_distances")

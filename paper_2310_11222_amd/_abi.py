@@ -62,6 +62,8 @@ SIGNATURES = {
     "nvd_project": (_I32, [_P, _I32, _P, _P, _I64, _P, _I64, _P, _P]),
     "nvd_distances": (_I32, [_P, _I32, _P, _P, _I64, C.POINTER(NvdOpts), _P, _P, _I64,
                              _P, _P]),
+    "nvd_distances_noalloc": (_I32, [_P, _I32, _P, _P, _I64, C.POINTER(NvdOpts), _P, _P, _I64,
+                                     _P, _P]),
     "nvd_pairwise": (_I32, [_P, _I32, _P, _I64, C.POINTER(NvdOpts), _P, _I64, _P, _I64,
                              _P, _P]),
     "nvd_grad_weights": (_I32, [_P, _I32, _P, _I64, _P, _P, _P]),
