@@ -18,9 +18,12 @@
 //
 // Order, for the GPU.  Vertices are eliminated in rounds: each round takes a
 // maximal set of live vertices no two of which are adjacent, greedily in
-// ascending current degree.  Eliminations within a round commute (none
-// touches another's neighbourhood), so the triangular solves process a
-// round in parallel: the depth of each solve is the number of rounds.
+// ascending current degree, among those of degree at most max(2, 2 d_min)
+// (d_min the smallest current degree), so that low degrees go first -- and a
+// graph that can be taken apart by degree-1 and degree-2 eliminations (a
+// tree, a cycle) is factored exactly.  Eliminations within a round commute
+// (none touches another's neighbourhood), so the triangular solves process
+// a round in parallel: the depth of each solve is the number of rounds.
 // Elimination preserves connectivity, and the last vertex of each component
 // ends with no neighbours: its pivot is 0 (the Laplacian's null space) and it
 // grounds its component.  After kAcholMaxRounds rounds the vertices still
@@ -129,7 +132,7 @@ HostFactor factor_graph(const DevGraph* g, int max_rounds) {
   std::vector<double> pre;
   for (int r = 0; r < max_rounds && !live.empty(); ++r) {
     // current degrees (merged, live neighbours only), candidates in
-    // ascending degree, ties by a hash of (vertex, round)
+    // ascending degree, ties in increasing vertex id
     int dmax = 0;
     for (int v : live) {
       compact(adj[v], alive);
@@ -140,11 +143,12 @@ HostFactor factor_graph(const DevGraph* g, int max_rounds) {
     for (int d = 0; d <= dmax; ++d) bucket_cnt[d + 1] += bucket_cnt[d];
     cand.resize(live.size());
     for (int v : live) cand[bucket_cnt[adj[v].size()]++] = v;
-    // (within a degree bucket, vertices stay in increasing id order)
-    // greedy maximal independent set
+    // greedy maximal independent set among the low-degree candidates
     next_live.clear();
     const int round_begin = (int)f.order.size();
+    const int dcap = std::max(2, 2 * (int)adj[cand[0]].size());
     for (int v : cand) {
+      if ((int)adj[v].size() > dcap) break;   // candidates ascend in degree
       if (blocked[v]) continue;
       f.order.push_back(v);
       blocked[v] = 1;
@@ -275,44 +279,103 @@ __global__ __launch_bounds__(256) void k_am_comp(int ncomp, int T, const int* __
   }
 }
 
-// Forward round: positions [p0, p1); y (kept in z) of each vertex from r,
-// minus its component mean, plus the pulls from earlier vertices.  T lanes
-// per vertex.
-template <typename V, typename C>
-__global__ __launch_bounds__(256) void k_am_fwd(int p0, int p1, int T, const int* __restrict__ order,
+// Pull of one vertex's list: sum over entries e in [lo, hi) taken by this
+// lane's sub-group (every NL-th, starting at j) of c_e * z[idx_e][col], four
+// entries' loads issued before their use.
+template <typename V, typename C, int T>
+__device__ __forceinline__ double pull(int lo, int hi, int j, int NL, int col,
+                                       const int* __restrict__ idx, const C* __restrict__ cf,
+                                       const V* __restrict__ z) {
+  double acc = 0.0;
+  int e = lo + j;
+  for (; e + 3 * NL < hi; e += 4 * NL) {
+    int ix[4];
+    double cv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ix[q] = idx[e + q * NL];
+      cv[q] = (double)cf[e + q * NL];
+    }
+    double zv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) zv[q] = (double)z[(long)ix[q] * T + col];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc += cv[q] * zv[q];
+  }
+  for (; e < hi; e += NL) acc += (double)cf[e] * (double)z[(long)idx[e] * T + col];
+  return acc;
+}
+
+// Forward round, positions [p0, p1): y_u (kept in z) = r_u - mean + pulls
+// from earlier vertices.  WAVE: one wave per vertex, its 64 / T lane
+// sub-groups splitting the list and meeting by shuffles (fixed order);
+// otherwise one 256-thread block per vertex (rounds with long lists), the
+// 256 / T sub-groups meeting in LDS.
+template <typename V, typename C, int T, bool WAVE>
+__global__ __launch_bounds__(256) void k_am_fwd(int p0, int p1, const int* __restrict__ order,
                                                 const int* __restrict__ in_off,
                                                 const int* __restrict__ in_idx,
                                                 const C* __restrict__ in_c, const V* __restrict__ r,
                                                 const int* __restrict__ comp,
                                                 const double* __restrict__ mean, V* __restrict__ z) {
-  const int vpb = 256 / T;
-  const int p = p0 + blockIdx.x * vpb + threadIdx.x / T;
-  const int c = threadIdx.x % T;
-  if (p >= p1) return;
-  const int u = order[p];
-  double acc = (double)r[(long)u * T + c] - mean[(long)comp[u] * kMaxTile + c];
-  for (int e = in_off[p]; e < in_off[p + 1]; ++e)
-    acc += (double)in_c[e] * (double)z[(long)in_idx[e] * T + c];
-  z[(long)u * T + c] = (V)acc;
+  constexpr int NL = (WAVE ? 64 : 256) / T;
+  __shared__ double sh[WAVE ? 1 : 256];
+  const int t = threadIdx.x;
+  const int lt = WAVE ? (t & 63) : t;
+  const int p = WAVE ? p0 + blockIdx.x * 4 + (t >> 6) : p0 + blockIdx.x;
+  if (p >= p1) return;                 // per wave (WAVE) or per block: no partial exits
+  const int c = lt % T, j = lt / T;
+  double acc = pull<V, C, T>(in_off[p], in_off[p + 1], j, NL, c, in_idx, in_c, z);
+  if constexpr (WAVE) {
+#pragma unroll
+    for (int off = T; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  } else {
+    sh[t] = acc;
+    __syncthreads();
+    for (int h = 128; h >= T; h >>= 1) {
+      if (t < h) sh[t] += sh[t + h];
+      __syncthreads();
+    }
+    acc = sh[t];
+  }
+  if (j == 0) {
+    const int u = order[p];
+    z[(long)u * T + c] = (V)(((double)r[(long)u * T + c] - mean[(long)comp[u] * kMaxTile + c]) + acc);
+  }
 }
 
-// Backward round: positions [p0, p1); z_v = y_v / W_v + pulls from later
-// vertices (final already).
-template <typename V, typename C>
-__global__ __launch_bounds__(256) void k_am_bwd(int p0, int p1, int T, const int* __restrict__ order,
+// Backward round, positions [p0, p1): z_v = y_v / W_v + pulls from later
+// vertices (already final); split as in the forward round.
+template <typename V, typename C, int T, bool WAVE>
+__global__ __launch_bounds__(256) void k_am_bwd(int p0, int p1, const int* __restrict__ order,
                                                 const int* __restrict__ out_off,
                                                 const int* __restrict__ out_idx,
                                                 const C* __restrict__ out_c,
                                                 const C* __restrict__ inv_pivot, V* __restrict__ z) {
-  const int vpb = 256 / T;
-  const int p = p0 + blockIdx.x * vpb + threadIdx.x / T;
-  const int c = threadIdx.x % T;
+  constexpr int NL = (WAVE ? 64 : 256) / T;
+  __shared__ double sh[WAVE ? 1 : 256];
+  const int t = threadIdx.x;
+  const int lt = WAVE ? (t & 63) : t;
+  const int p = WAVE ? p0 + blockIdx.x * 4 + (t >> 6) : p0 + blockIdx.x;
   if (p >= p1) return;
-  const int v = order[p];
-  double acc = (double)z[(long)v * T + c] * (double)inv_pivot[p];
-  for (int e = out_off[p]; e < out_off[p + 1]; ++e)
-    acc += (double)out_c[e] * (double)z[(long)out_idx[e] * T + c];
-  z[(long)v * T + c] = (V)acc;
+  const int c = lt % T, j = lt / T;
+  double acc = pull<V, C, T>(out_off[p], out_off[p + 1], j, NL, c, out_idx, out_c, z);
+  if constexpr (WAVE) {
+#pragma unroll
+    for (int off = T; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  } else {
+    sh[t] = acc;
+    __syncthreads();
+    for (int h = 128; h >= T; h >>= 1) {
+      if (t < h) sh[t] += sh[t + h];
+      __syncthreads();
+    }
+    acc = sh[t];
+  }
+  if (j == 0) {
+    const int v = order[p];
+    z[(long)v * T + c] = (V)((double)z[(long)v * T + c] * (double)inv_pivot[p] + acc);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -371,6 +434,15 @@ nvd_status ensure_achol(DevGraph* g) {
   ap->remainder = f.remainder;
   ap->nnz = (int64_t)nf;
   ap->round_off = f.round_off;
+  const int nr = (int)f.round_off.size() - 1;
+  ap->fwd_max.assign(nr, 0);
+  ap->bwd_max.assign(nr, 0);
+  for (int k = 0; k < nr; ++k) {
+    for (int p = f.round_off[k]; p < f.round_off[k + 1]; ++p) {
+      ap->fwd_max[k] = std::max(ap->fwd_max[k], in_off[p + 1] - in_off[p]);
+      ap->bwd_max[k] = std::max(ap->bwd_max[k], f.col_off[p + 1] - f.col_off[p]);
+    }
+  }
   nvd_status st = NVD_OK;
   auto alloc = [&](void** p, size_t bytes) {
     if (st != NVD_OK) return;
@@ -421,6 +493,39 @@ nvd_status ensure_achol(DevGraph* g) {
   return NVD_OK;
 }
 
+// Rounds whose longest pull list reaches this take a block per vertex.
+constexpr int kAmLongList = 256;
+
+template <typename V, int T>
+static void achol_rounds(const DevGraph* g, const V* r, V* z, hipStream_t s) {
+  const AcholPre* ap = g->achol;
+  const int nr = (int)ap->round_off.size() - 1;   // rounds, then the remainder
+  using C = V;
+  const C* in_c = sizeof(V) == 8 ? (const C*)ap->in_c64 : (const C*)ap->in_c32;
+  const C* out_c = sizeof(V) == 8 ? (const C*)ap->out_c64 : (const C*)ap->out_c32;
+  const C* ip = sizeof(V) == 8 ? (const C*)ap->ip64 : (const C*)ap->ip32;
+  for (int k = 0; k < nr; ++k) {
+    const int p0 = ap->round_off[k], p1 = ap->round_off[k + 1];
+    if (p1 <= p0) continue;
+    if (ap->fwd_max[k] >= kAmLongList)
+      k_am_fwd<V, C, T, false><<<p1 - p0, 256, 0, s>>>(p0, p1, ap->order, ap->in_off, ap->in_idx, in_c,
+                                                       r, g->comp, ap->mean, z);
+    else
+      k_am_fwd<V, C, T, true><<<(p1 - p0 + 3) / 4, 256, 0, s>>>(p0, p1, ap->order, ap->in_off,
+                                                                ap->in_idx, in_c, r, g->comp, ap->mean, z);
+  }
+  for (int k = nr - 1; k >= 0; --k) {
+    const int p0 = ap->round_off[k], p1 = ap->round_off[k + 1];
+    if (p1 <= p0) continue;
+    if (ap->bwd_max[k] >= kAmLongList)
+      k_am_bwd<V, C, T, false><<<p1 - p0, 256, 0, s>>>(p0, p1, ap->order, ap->out_off, ap->out_idx,
+                                                       out_c, ip, z);
+    else
+      k_am_bwd<V, C, T, true><<<(p1 - p0 + 3) / 4, 256, 0, s>>>(p0, p1, ap->order, ap->out_off,
+                                                                ap->out_idx, out_c, ip, z);
+  }
+}
+
 template <typename V>
 static nvd_status achol_solve_t(DevGraph* g, int T, const V* r, V* z, hipStream_t s) {
   AcholPre* ap = g->achol;
@@ -433,23 +538,14 @@ static nvd_status achol_solve_t(DevGraph* g, int T, const V* r, V* z, hipStream_
     k_am_comp<V><<<std::min(g->n_comp, 4096), 256, 0, s>>>(g->n_comp, T, g->comp_perm, g->comp_off, r,
                                                            ap->mean);
   }
-  const int vpb = 256 / T;
-  const int nr = (int)ap->round_off.size() - 1;   // rounds, then the remainder
-  using C = V;
-  const C* in_c = sizeof(V) == 8 ? (const C*)ap->in_c64 : (const C*)ap->in_c32;
-  const C* out_c = sizeof(V) == 8 ? (const C*)ap->out_c64 : (const C*)ap->out_c32;
-  const C* ip = sizeof(V) == 8 ? (const C*)ap->ip64 : (const C*)ap->ip32;
-  for (int k = 0; k < nr; ++k) {
-    const int p0 = ap->round_off[k], p1 = ap->round_off[k + 1];
-    if (p1 <= p0) continue;
-    k_am_fwd<V, C><<<(p1 - p0 + vpb - 1) / vpb, 256, 0, s>>>(p0, p1, T, ap->order, ap->in_off,
-                                                             ap->in_idx, in_c, r, g->comp, ap->mean, z);
-  }
-  for (int k = nr - 1; k >= 0; --k) {
-    const int p0 = ap->round_off[k], p1 = ap->round_off[k + 1];
-    if (p1 <= p0) continue;
-    k_am_bwd<V, C><<<(p1 - p0 + vpb - 1) / vpb, 256, 0, s>>>(p0, p1, T, ap->order, ap->out_off,
-                                                             ap->out_idx, out_c, ip, z);
+  switch (T) {
+    case 1: achol_rounds<V, 1>(g, r, z, s); break;
+    case 2: achol_rounds<V, 2>(g, r, z, s); break;
+    case 4: achol_rounds<V, 4>(g, r, z, s); break;
+    case 8: achol_rounds<V, 8>(g, r, z, s); break;
+    case 16: achol_rounds<V, 16>(g, r, z, s); break;
+    case 32: achol_rounds<V, 32>(g, r, z, s); break;
+    default: achol_rounds<V, 64>(g, r, z, s); break;
   }
   NVD_HIP(hipGetLastError());
   return NVD_OK;

@@ -128,6 +128,8 @@ struct AcholPre {
   double* mean = nullptr;      // [n_comp][kMaxTile]
   double* part = nullptr;      // [blocks][kMaxTile]
   std::vector<int> round_off;  // host: positions of each round, last range = remainder
+  std::vector<int> fwd_max;    // host: longest forward pull list of each round
+  std::vector<int> bwd_max;    // host: longest backward pull list of each round
   int rounds = 0;
   int grounds = 0;
   int remainder = 0;
