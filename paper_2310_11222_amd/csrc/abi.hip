@@ -359,7 +359,10 @@ nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double*
     while (T > k - c0) T >>= 1;
     sp.nl = tuned_nl(g, o.precision, T);
     st = ensure_workspace(g, T, o.precision == NVD_MIXED);
-    if (st == NVD_OK)
+    if (st == NVD_OK && small_eligible(g, T, sp))
+      st = solve_small(g, T, P + c0, Q + c0, ld, sp, d_out + c0, X ? X + c0 : nullptr, ldx,
+                       g->ws->info, s);
+    else if (st == NVD_OK)
       st = solve_tile(g, T, P + c0, Q + c0, ld, sp, d_out + c0, X ? X + c0 : nullptr, ldx,
                       g->ws->info, s);
     if (st == NVD_OK) {

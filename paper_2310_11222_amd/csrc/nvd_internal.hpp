@@ -255,6 +255,12 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
 nvd_status solve_tile_ws(DevGraph* g, Workspace* ws, int T, const double* P, const double* Q,
                          int64_t ld, const SolveParams& sp, double* d_out, double* X,
                          int64_t ldx, nvd_pair_info* info_dev, hipStream_t s);
+// One launch per tile for small connected graphs (small.hip): the whole solve
+// in one block.  NVD_SMALL=0 in the environment turns the path off.
+bool small_eligible(const DevGraph* g, int T, const SolveParams& sp);
+nvd_status solve_small(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
+                       const SolveParams& sp, double* d_out, double* X, int64_t ldx,
+                       nvd_pair_info* info_dev, hipStream_t s);
 // Tile for k pairs without timing anything: the autotuner's cached choice,
 // else the fixed heuristic.
 int untimed_tile(const DevGraph* g, int k, int precision);
