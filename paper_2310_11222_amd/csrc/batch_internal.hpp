@@ -71,6 +71,12 @@ struct nvd_batch {
   size_t sstate_cap = 0;
   int* h_poll = nullptr;               // pinned host words for polling
   int64_t sweeps = 0;
+  // sweep solver: a chunk of inner iterations (apply, update, direction
+  // kernels) captured in a hipGraph, replayed while its arguments match
+  hipGraph_t sw_graph = nullptr;
+  hipGraphExec_t sw_exec = nullptr;
+  std::vector<unsigned char> sw_key;
+  bool sw_capture_failed = false;
 };
 
 static void batch_drop_graph(nvd_batch* b) {
@@ -81,8 +87,17 @@ static void batch_drop_graph(nvd_batch* b) {
   b->key.clear();
 }
 
+static void batch_drop_sweep_graph(nvd_batch* b) {
+  if (b->sw_exec) (void)hipGraphExecDestroy(b->sw_exec);
+  if (b->sw_graph) (void)hipGraphDestroy(b->sw_graph);
+  b->sw_exec = nullptr;
+  b->sw_graph = nullptr;
+  b->sw_key.clear();
+}
+
 static inline void batch_free(nvd_batch* b) {
   batch_drop_graph(b);
+  batch_drop_sweep_graph(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   void* ptrs[] = {b->rp, b->ci, b->w64, b->w32, b->invd64, b->invd32,
                   b->long_rows, b->b64, b->x64, b->r64, b->cv, b->rv, b->pv, b->qv, b->gd,

@@ -18,6 +18,8 @@
 // CG with residual restarts (FP64), as in the single-graph solver; the
 // distance is d^2 = delta_bar^T x + x^T (delta_bar - L x) in FP64.
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 #include <cmath>
 #include <vector>
 
@@ -867,6 +869,58 @@ static nvd_status poll_counts(nvd_batch* b, const SArgs& a, hipStream_t s, int* 
   return NVD_OK;
 }
 
+// Inner iterations per captured chunk: kCapIters x (apply, update,
+// direction).  The kernels skip graphs whose pairs have all converged, so a
+// chunk that runs past the last active iteration costs only its launches.
+constexpr int kCapIters = 8;
+
+// Launches one captured chunk of inner iterations, capturing it first when
+// no graph exists for these arguments (kernel arguments are fixed in the
+// graph: the key is the whole argument block, the tile and the element type).
+// *launched is false if capture is unavailable; the caller then launches the
+// kernels directly.
+template <int T, typename V>
+static nvd_status launch_captured_chunk(nvd_batch* b, const SArgs& a, int grid, hipStream_t s,
+                                        bool* launched) {
+  *launched = false;
+  if (b->sw_capture_failed) return NVD_OK;
+  std::vector<unsigned char> key(sizeof(SArgs) + 3 * sizeof(int));
+  std::memcpy(key.data(), &a, sizeof(SArgs));
+  const int extra[3] = {T, (int)sizeof(V), grid};
+  std::memcpy(key.data() + sizeof(SArgs), extra, sizeof(extra));
+  if (!b->sw_exec || b->sw_key != key) {
+    batch_drop_sweep_graph(b);
+    if (!b->cap_stream) NVD_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      for (int it = 0; it < kCapIters; ++it) {
+        ks_spmm<V, T, EPI_CG, 1><<<grid, SBS, 0, b->cap_stream>>>(a);
+        ks_update<V, T><<<grid, SBS, 0, b->cap_stream>>>(a);
+        ks_direction<V, T><<<grid, SBS, 0, b->cap_stream>>>(a);
+      }
+    }
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &gr);
+    if (e == hipSuccess && e2 == hipSuccess && gr &&
+        hipGraphInstantiate(&b->sw_exec, gr, nullptr, nullptr, 0) == hipSuccess) {
+      b->sw_graph = gr;
+      b->sw_key = key;
+      ++b->captures;
+    } else {
+      if (gr) (void)hipGraphDestroy(gr);
+      b->sw_exec = nullptr;
+      b->sw_capture_failed = true;     // direct launches from now on
+      (void)hipGetLastError();
+      return NVD_OK;
+    }
+  } else {
+    ++b->replays;
+  }
+  NVD_HIP(hipGraphLaunch(b->sw_exec, s));
+  *launched = true;
+  return NVD_OK;
+}
+
 template <int T, typename V>
 static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_opts& o,
                           const double* P, const double* Q, double* d_out, double* X,
@@ -1009,6 +1063,8 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
   a.irtol2 = mixed ? o.inner_rtol * o.inner_rtol : o.rtol * o.rtol;
   a.max_iter = o.max_iter;
   a.max_refine = mixed ? o.max_refine : std::max(2, std::min(o.max_refine, 3));
+  const char* ge = std::getenv("NVD_BATCH_GRAPH");
+  const bool use_graph = !(ge && ge[0] == '0');
   // a multiple of 8 blocks (the same number on every XCD): one per chunk
   int xmax = 0;
   for (int q = 0; q < 8; ++q) xmax = std::max(xmax, b->xcount[q]);
@@ -1031,10 +1087,16 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
     }
     ks_inner_init<V, T><<<grid, SBS, 0, s>>>(a, step == 0 ? 1 : 0);
     int done = 0;
-    int chunk = 8;
+    int chunk = kCapIters;
     while (done < a.max_iter) {
       const int todo = std::min(chunk, a.max_iter - done);
-      for (int it = 0; it < todo; ++it) {
+      int it = 0;
+      for (; use_graph && it + kCapIters <= todo; it += kCapIters) {
+        bool launched = false;
+        NVD_TRY((launch_captured_chunk<T, V>(b, a, grid, s, &launched)));
+        if (!launched) break;
+      }
+      for (; it < todo; ++it) {
         ks_spmm<V, T, EPI_CG, 1><<<grid, SBS, 0, s>>>(a);
         ks_update<V, T><<<grid, SBS, 0, s>>>(a);
         ks_direction<V, T><<<grid, SBS, 0, s>>>(a);
@@ -1043,7 +1105,8 @@ static nvd_status sweep_t(nvd_batch* b, const std::vector<int>& ks, const nvd_op
       done += todo;
       NVD_TRY(poll_counts(b, a, s, &n_act, &n_oact));
       if (n_act == 0) break;
-      chunk = std::min(32, std::max(8, done / 2));
+      // chunks of whole captured sub-chunks, growing with the iterations seen
+      chunk = std::min(4 * kCapIters, std::max(kCapIters, done / 2 / kCapIters * kCapIters));
     }
     ks_accum<V, T><<<grid, SBS, 0, s>>>(a);
   }
