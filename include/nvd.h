@@ -143,7 +143,9 @@ typedef struct nvd_opts {
 
 typedef struct nvd_pair_info {
   int32_t status;       /* NVD_OK, NVD_E_NOCONV or NVD_E_BREAKDOWN
-                           (NVD_E_DEVICE: the persistent batch launch failed) */
+                           (NVD_E_DEVICE: a persistent launch -- the batch's,
+                           or the single-launch solve of a small graph -- gave
+                           up at a barrier; its outputs are then meaningless) */
   int32_t iters;        /* CG iterations (all inner solves summed) */
   int32_t refine_steps; /* MIXED outer steps (0 for FP64) */
   int32_t flags;        /* NVD_INFO_FP64_FALLBACK: the mixed solve stalled
@@ -231,7 +233,11 @@ nvd_status nvd_project(nvd_graph* g, int32_t k, const double* P,
  *   delta_j (mean zero on every component).  With NVD_WARM_START it also
  *   supplies the starting guess.
  * info: host array of k nvd_pair_info or NULL.
- * Synchronous with respect to `stream` (see Streams). */
+ * Synchronous with respect to `stream` (see Streams).  On a connected graph
+ * with the Jacobi preconditioner and no warm start, a tile of up to about
+ * 1e6 vector elements (n times the tile) is solved by one kernel launch
+ * (one block, or a cooperative launch of up to 256 blocks); NVD_E_DEVICE if
+ * that launch gives up at a barrier. */
 nvd_status nvd_distances(nvd_graph* g, int32_t k, const double* P,
                          const double* Q, int64_t ld, const nvd_opts* opts,
                          double* d_out, double* X_inout, int64_t ldx,

@@ -359,8 +359,9 @@ nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double*
     while (T > k - c0) T >>= 1;
     sp.nl = tuned_nl(g, o.precision, T);
     st = ensure_workspace(g, T, o.precision == NVD_MIXED);
-    if (st == NVD_OK && small_eligible(g, T, sp))
-      st = solve_small(g, T, P + c0, Q + c0, ld, sp, d_out + c0, X ? X + c0 : nullptr, ldx,
+    const int nb = st == NVD_OK ? small_blocks(g, T, sp) : 0;
+    if (st == NVD_OK && nb > 0)
+      st = solve_small(g, T, nb, P + c0, Q + c0, ld, sp, d_out + c0, X ? X + c0 : nullptr, ldx,
                        g->ws->info, s);
     else if (st == NVD_OK)
       st = solve_tile(g, T, P + c0, Q + c0, ld, sp, d_out + c0, X ? X + c0 : nullptr, ldx,
@@ -378,6 +379,11 @@ nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double*
   }
   if (st != NVD_OK) return st;
   for (int j = 0; j < k; ++j) {
+    if (hinfo[j].status == NVD_E_DEVICE) {
+      if (info) std::copy(hinfo.begin(), hinfo.end(), info);
+      set_error("nvd_distances: a grid barrier of the single-launch solve gave up");
+      return NVD_E_DEVICE;
+    }
     if (hinfo[j].status == NVD_E_BREAKDOWN) agg = NVD_E_BREAKDOWN;
     else if (hinfo[j].status == NVD_E_NOCONV && agg == NVD_OK) agg = NVD_E_NOCONV;
   }

@@ -62,7 +62,7 @@ nvd_status free_workspace(Workspace* ws) {
   if (!ws) return NVD_OK;
   void* ptrs[] = {ws->b64, ws->x64, ws->r64, ws->p64, ws->q64, ws->x32, ws->r32, ws->p32,
                   ws->q32, ws->comp_mean, ws->cs, ws->info, ws->red.part1, ws->red.part2,
-                  ws->red.tick1, ws->red.tick2};
+                  ws->red.tick1, ws->red.tick2, ws->msync, ws->hq};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (ws->h_pinned) (void)hipHostFree(ws->h_pinned);
@@ -111,6 +111,7 @@ nvd_status ensure_workspace(DevGraph* g, int tile, bool need32) {
   chk(dalloc(&ws->red.part2, (size_t)(kMaxBlocks / kGrp) * stride, by));
   chk(dalloc(&ws->red.tick1, (size_t)(kMaxBlocks / kGrp), by));
   chk(dalloc(&ws->red.tick2, 1, by));
+  chk(dalloc(&ws->msync, 64, by));
   if (st == NVD_OK) {
     hipError_t e = hipHostMalloc((void**)&ws->h_pinned, 64, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -526,6 +527,7 @@ nvd_status graph_destroy(DevGraph* g) {
   if (g->ws) free_workspace(g->ws);
   free_tree(g->tree);
   free_achol(g->achol);
+  if (g->heavy) (void)hipFree(g->heavy);
   free_graph_arrays(g);
   delete g;
   return NVD_OK;

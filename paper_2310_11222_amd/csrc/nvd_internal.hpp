@@ -171,6 +171,10 @@ struct DevGraph {
   int tuned_nl[2][8] = {};     // [precision][log2 tile] -> neighbour lanes (0 = default)
   TreePre* tree = nullptr;     // spanning forest, built when first needed
   AcholPre* achol = nullptr;   // approximate-Cholesky factor, built when first needed
+  int* heavy = nullptr;        // rows walked by a whole wave in the single-launch solve
+  int n_heavy = -1;            // (built when first needed, longest first; -1: not yet)
+  int heavy_base = 0;          // degree threshold the list was built for
+  std::vector<int> heavy_deg_desc;  // host: their degrees
 };
 
 struct Workspace {
@@ -191,6 +195,8 @@ struct Workspace {
   ColState* cs = nullptr;
   nvd_pair_info* info = nullptr;  // [kMaxTile] per-pair results of one tile
   GridRed red{};
+  unsigned* msync = nullptr;   // [2] grid barrier of the multi-block small solve
+  double* hq = nullptr;        // n x tile: q of heavy rows in the single-launch solve (lazy)
   int* h_pinned = nullptr;     // pinned host words for polling
   int64_t bytes = 0;
 };
@@ -255,10 +261,12 @@ nvd_status solve_tile(DevGraph* g, int T, const double* P, const double* Q, int6
 nvd_status solve_tile_ws(DevGraph* g, Workspace* ws, int T, const double* P, const double* Q,
                          int64_t ld, const SolveParams& sp, double* d_out, double* X,
                          int64_t ldx, nvd_pair_info* info_dev, hipStream_t s);
-// One launch per tile for small connected graphs (small.hip): the whole solve
-// in one block.  NVD_SMALL=0 in the environment turns the path off.
-bool small_eligible(const DevGraph* g, int T, const SolveParams& sp);
-nvd_status solve_small(DevGraph* g, int T, const double* P, const double* Q, int64_t ld,
+// One launch per tile for small and mid-size connected graphs (small.hip):
+// small_blocks gives the launch's block count (1: one block; more: a
+// cooperative launch with grid barriers) or 0 where the multi-kernel path
+// runs.  NVD_SMALL=0 in the environment turns the path off.
+int small_blocks(DevGraph* g, int T, const SolveParams& sp);
+nvd_status solve_small(DevGraph* g, int T, int nb, const double* P, const double* Q, int64_t ld,
                        const SolveParams& sp, double* d_out, double* X, int64_t ldx,
                        nvd_pair_info* info_dev, hipStream_t s);
 // Tile for k pairs without timing anything: the autotuner's cached choice,
