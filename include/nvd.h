@@ -91,7 +91,8 @@ enum {
   NVD_BATCH_PERSISTENT = 2u,/* nvd_batch_distances: the single persistent
                                launch instead of the sweep solver */
   NVD_PRECOND_TREE = 4u,    /* nvd_distances / nvd_pairwise: precondition CG
-                               with a spanning forest of the graph (exact
+                               with the maximum-weight spanning forest of the
+                               graph (breadth-first on unit weights; exact
                                tree solve; a tree-based solver is one of the
                                solvers compared in Table 1, "Aug Tree")
                                instead of the Jacobi diagonal; for very sparse

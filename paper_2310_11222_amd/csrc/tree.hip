@@ -1,7 +1,9 @@
 // Spanning-tree preconditioner: z = L_T^+ r for a spanning forest T of the
-// graph (the tree-based preconditioners of section 3.2; here a plain
-// breadth-first spanning forest, without the augmentation of the paper's
-// "Aug Tree" solver).
+// graph (the tree preconditioner family of Table 1's "Aug Tree" solver,
+// without its augmentation): on unit weights the breadth-first forest from
+// each component's smallest node; on weighted graphs, of that forest and the
+// maximum-weight spanning forest, the one whose off-forest edges have the
+// smaller total stretch.
 //
 // On a tree, L_T x = r has a closed solution (the flow formula): the flow on
 // the edge from v to its parent is the sum f_v of r over v's subtree, the
@@ -28,6 +30,7 @@
 // per component, which does not change r^T z for r orthogonal to the
 // constants and which the solver's projections remove.
 #include <algorithm>
+#include <queue>
 #include <vector>
 
 #include "device_common.hpp"
@@ -46,20 +49,19 @@ static int scan_chunk(long rows) {
 }
 
 // ---------------------------------------------------------------------------
-// host: spanning forest and Euler tour
+// host: spanning forests, their stretch, the Euler tour
 // ---------------------------------------------------------------------------
-static nvd_status build_tree(DevGraph* g) {
+// Breadth-first forest, a root per component: its smallest node.
+static int forest_bfs(const DevGraph* g, std::vector<int>& parent, std::vector<double>& pw) {
   const int n = g->n;
   const std::vector<int>& rp = g->h_rp;
   const std::vector<int>& ci = g->h_ci;
   const bool weighted = !g->h_w.empty();
-  std::vector<int> parent(n, -1);
-  std::vector<double> pw(n, 0.0);
   std::vector<char> seen(n, 0);
   std::vector<int> queue;
   queue.reserve(n);
   int tree_edges = 0;
-  for (int s = 0; s < n; ++s) {          // a root per component: its smallest node
+  for (int s = 0; s < n; ++s) {
     if (seen[s]) continue;
     seen[s] = 1;
     size_t head = queue.size();
@@ -77,16 +79,142 @@ static nvd_status build_tree(DevGraph* g) {
       }
     }
   }
-  // children lists (CSR), then an iterative depth-first Euler tour
-  std::vector<int> coff(n + 1, 0), kids(std::max(tree_edges, 1));
+  return tree_edges;
+}
+
+// Maximum-weight spanning forest: Prim from each component's smallest node,
+// the heaviest edge leaving the tree first; among equal weights the earliest
+// discovered edge (so equal weights give the breadth-first forest).
+static int forest_max_weight(const DevGraph* g, std::vector<int>& parent, std::vector<double>& pw) {
+  const int n = g->n;
+  const std::vector<int>& rp = g->h_rp;
+  const std::vector<int>& ci = g->h_ci;
+  struct Cand {
+    double w;
+    long seq;
+    int v, u;
+  };
+  auto lower = [](const Cand& a, const Cand& b) {
+    return a.w < b.w || (a.w == b.w && a.seq > b.seq);
+  };
+  std::priority_queue<Cand, std::vector<Cand>, decltype(lower)> heap(lower);
+  std::vector<char> seen(n, 0);
+  long seq = 0;
+  int tree_edges = 0;
+  auto reach = [&](int v) {
+    for (int e = rp[v]; e < rp[v + 1]; ++e)
+      if (!seen[ci[e]]) heap.push(Cand{g->h_w[e], seq++, v, ci[e]});
+  };
+  for (int s = 0; s < n; ++s) {
+    if (seen[s]) continue;
+    seen[s] = 1;
+    reach(s);
+    while (!heap.empty()) {
+      const Cand c = heap.top();
+      heap.pop();
+      if (seen[c.u]) continue;
+      seen[c.u] = 1;
+      parent[c.u] = c.v;
+      pw[c.u] = c.w;
+      ++tree_edges;
+      reach(c.u);
+    }
+  }
+  return tree_edges;
+}
+
+// Children of every node in a forest (CSR by parent).
+static void forest_children(int n, const std::vector<int>& parent, std::vector<int>& coff,
+                            std::vector<int>& kids) {
+  coff.assign(n + 1, 0);
   for (int v = 0; v < n; ++v)
     if (parent[v] >= 0) ++coff[parent[v] + 1];
   for (int v = 0; v < n; ++v) coff[v + 1] += coff[v];
-  {
-    std::vector<int> fill(coff.begin(), coff.end() - 1);
-    for (int v = 0; v < n; ++v)
-      if (parent[v] >= 0) kids[fill[parent[v]]++] = v;
+  kids.assign(std::max(coff[n], 1), 0);
+  std::vector<int> fill(coff.begin(), coff.end() - 1);
+  for (int v = 0; v < n; ++v)
+    if (parent[v] >= 0) kids[fill[parent[v]]++] = v;
+}
+
+// Total stretch of the edges off a forest: the sum over them of w_e times
+// the resistance of the forest path between their ends, which bounds the
+// condition number of the forest-preconditioned Laplacian.  Forest paths
+// through lowest common ancestors, found offline (Tarjan: a depth-first
+// walk that merges each finished subtree into its parent's set).
+static double forest_stretch(const DevGraph* g, const std::vector<int>& parent,
+                             const std::vector<double>& pw) {
+  const int n = g->n;
+  const std::vector<int>& rp = g->h_rp;
+  const std::vector<int>& ci = g->h_ci;
+  std::vector<int> coff, kids;
+  forest_children(n, parent, coff, kids);
+  std::vector<int> uf(n), anc(n);
+  std::vector<char> done(n, 0);
+  std::vector<double> dist(n, 0.0);
+  auto find = [&](int v) {
+    while (uf[v] != v) {
+      uf[v] = uf[uf[v]];
+      v = uf[v];
+    }
+    return v;
+  };
+  double stretch = 0.0;
+  std::vector<std::pair<int, int>> stack;
+  for (int root = 0; root < n; ++root) {
+    if (parent[root] >= 0) continue;
+    uf[root] = root;
+    anc[root] = root;
+    stack.emplace_back(root, coff[root]);
+    while (!stack.empty()) {
+      auto& top = stack.back();
+      const int v = top.first;
+      if (top.second < coff[v + 1]) {
+        const int c = kids[top.second++];
+        dist[c] = dist[v] + 1.0 / pw[c];
+        uf[c] = c;
+        anc[c] = c;
+        stack.emplace_back(c, coff[c]);
+        continue;
+      }
+      done[v] = 1;
+      for (int e = rp[v]; e < rp[v + 1]; ++e) {
+        const int u = ci[e];
+        if (!done[u] || u == v || parent[u] == v || parent[v] == u) continue;
+        const int l = anc[find(u)];
+        stretch += g->h_w[e] * (dist[u] + dist[v] - 2.0 * dist[l]);
+      }
+      stack.pop_back();
+      if (parent[v] >= 0) {
+        uf[find(v)] = find(parent[v]);
+        anc[find(parent[v])] = parent[v];
+      }
+    }
   }
+  return stretch;
+}
+
+// host: spanning forest (the breadth-first one on unit weights; on weighted
+// graphs, of the breadth-first and the maximum-weight forest the one of
+// smaller total stretch) and its Euler tour
+static nvd_status build_tree(DevGraph* g) {
+  const int n = g->n;
+  const bool weighted = !g->h_w.empty();
+  std::vector<int> parent(n, -1);
+  std::vector<double> pw(n, 0.0);
+  int tree_edges = forest_bfs(g, parent, pw);
+  if (weighted) {
+    std::vector<int> parent2(n, -1);
+    std::vector<double> pw2(n, 0.0);
+    const int e2 = forest_max_weight(g, parent2, pw2);
+    if (forest_stretch(g, parent2, pw2) < forest_stretch(g, parent, pw)) {
+      parent.swap(parent2);
+      pw.swap(pw2);
+      tree_edges = e2;
+    }
+  }
+  // children lists (CSR), then an iterative depth-first Euler tour
+  std::vector<int> coff, kids;
+  forest_children(n, parent, coff, kids);
   std::vector<int> tin(n), tout(n), root_of(n);
   std::vector<std::pair<int, int>> stack;
   int t = 0;

@@ -104,6 +104,43 @@ def test_general_weighted_disconnected_graph(precision, rtol, tol):
     assert all(i["status"] == 0 for i in info)
 
 
+@pytest.mark.parametrize("precision,rtol,tol", PREC)
+def test_weighted_graph_takes_the_maximum_weight_forest(precision, rtol, tol):
+    """A heavy path (weights 1e4) threaded through light random edges
+    (weights 1e-2, one per 20 nodes, many of them shortcuts that a
+    breadth-first forest from node 0 would take): the maximum-weight forest
+    is the path, off which only light edges lie, so tree-PCG converges in a
+    few iterations; a breadth-first forest would leave heavy path edges off
+    the tree and need hundreds."""
+    rng = np.random.default_rng(11)
+    n = 50_000
+    perm = rng.permutation(n)
+    pu, pv = perm[:-1], perm[1:]
+    m_extra = n // 20
+    xu = rng.integers(0, n, m_extra)
+    xv = rng.integers(0, n, m_extra)
+    keep = xu != xv
+    eu = np.concatenate([pu, xu[keep]])
+    ev = np.concatenate([pv, xv[keep]])
+    a, b = np.minimum(eu, ev), np.maximum(eu, ev)
+    key = a * n + b
+    _, first = np.unique(key, return_index=True)
+    first = np.sort(first)                     # path edges come first and are kept
+    w = np.concatenate([np.full(n - 1, 1e4), np.full(int(keep.sum()), 1e-2)])[first]
+    g = Graph(n, a[first], b[first], w)
+    P, Q = sparse_support_pairs(n, 8, 0.05, rng)
+    say("max-weight forest", precision)
+    dg = dev_graph(g)
+    d, _, info = dg.distances(P, Q, precision=precision, rtol=rtol, precond="tree")
+    # the exact grounded route: Jacobi-PCG stalls on a weight ratio of 1e6
+    ref = oracle.ge_grounded(g.n, g.row_ptr, g.col_idx, g.w, P, Q, sparse=True)["d"]
+    assert rel_err(d.cpu().numpy(), ref).max() <= tol
+    assert all(i["status"] == 0 for i in info)
+    # all inner solves summed in mixed precision
+    assert max(i["iters"] for i in info) <= (40 if precision == "fp64" else 120), \
+        [i["iters"] for i in info]
+
+
 @pytest.mark.parametrize("tile", [1, 2, 4, 8, 16, 32, 64])
 def test_tree_every_tile_width(tile):
     """The tour scans split each chunk over 256/T lanes per column: every
