@@ -91,17 +91,20 @@ enum {
   NVD_BATCH_PERSISTENT = 2u,/* nvd_batch_distances: the single persistent
                                launch instead of the sweep solver */
   NVD_PRECOND_TREE = 4u,    /* nvd_distances / nvd_pairwise: precondition CG
-                               with the maximum-weight spanning forest of the
-                               graph (breadth-first on unit weights; exact
-                               tree solve; a tree-based solver is one of the
-                               solvers compared in Table 1, "Aug Tree")
-                               instead of the Jacobi diagonal; for very sparse
-                               graphs.  Not for batches. */
+                               with an augmented spanning forest (Table 1's
+                               "Aug Tree"): a breadth-first or maximum-weight
+                               forest, whichever has the smaller stretch,
+                               plus up to 256 off-forest edges of largest
+                               stretch, solved exactly (forest solve and a
+                               rank-k correction); instead of the Jacobi
+                               diagonal, for sparse graphs, above all with
+                               heavy-tailed weights.  Not for batches. */
   NVD_PRECOND_AUTO = 8u,    /* nvd_distances / nvd_pairwise: the spanning
                                forest when at most n/100 edges lie off it
                                (m - n + c <= n / 100 for m edges and c
                                components: tree PCG then needs at most that
-                               many iterations plus one in exact arithmetic),
+                               many iterations plus one in exact arithmetic)
+                               or when the augmentation takes all of them,
                                else the Jacobi diagonal.  Batches always use
                                the Jacobi diagonal under this flag. */
   NVD_OUT_DSQ = 16u,        /* nvd_distances: d_out receives d^2 (the

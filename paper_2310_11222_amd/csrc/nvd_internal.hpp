@@ -107,6 +107,15 @@ struct TreePre {
   double* part = nullptr;      // [chunks][cap_tile] scan offsets
   int cap_tile = 0;
   int n_tree_edges = 0;
+  // augmentation: k off-forest edges solved exactly with the forest
+  // (Woodbury: M^+ = L_T^+ - Y C^-1 Y^T, Y = L_T^+ U, C = W^-1 + U^T Y)
+  int k_aug = 0;
+  std::vector<int> aug_u, aug_v;  // host: the edges' ends
+  std::vector<double> aug_w;      // host: their weights
+  int* aug_uv = nullptr;          // [2k] u then v
+  double* aug_Y = nullptr;        // [n][k] L_T^+ U (built with the first tile)
+  double* aug_Cinv = nullptr;     // [k][k] C^-1
+  double* aug_st = nullptr;       // [2][k][kMaxTile] U^T z, then C^-1 U^T z
 };
 
 // Approximate-Cholesky factor for its preconditioner (built on first use):

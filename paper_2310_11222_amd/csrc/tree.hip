@@ -1,9 +1,13 @@
-// Spanning-tree preconditioner: z = L_T^+ r for a spanning forest T of the
-// graph (the tree preconditioner family of Table 1's "Aug Tree" solver,
-// without its augmentation): on unit weights the breadth-first forest from
+// Augmented spanning-tree preconditioner (Table 1's "Aug Tree"): z = L_H^+ r
+// for H = a spanning forest T of the graph plus the k off-forest edges of
+// largest stretch.  T is, on unit weights, the breadth-first forest from
 // each component's smallest node; on weighted graphs, of that forest and the
 // maximum-weight spanning forest, the one whose off-forest edges have the
-// smaller total stretch.
+// smaller total stretch.  The k edges are solved with the forest exactly by
+// the Woodbury identity: with U their signed incidence columns and W their
+// weights, L_H^+ = L_T^+ - Y C^-1 Y^T, Y = L_T^+ U (k forest solves at
+// set-up), C = W^-1 + U^T Y (k x k, inverted on the host); one application is
+// a forest solve, s = U^T z, t = C^-1 s and z -= Y t.
 //
 // On a tree, L_T x = r has a closed solution (the flow formula): the flow on
 // the edge from v to its parent is the sum f_v of r over v's subtree, the
@@ -30,6 +34,8 @@
 // per component, which does not change r^T z for r orthogonal to the
 // constants and which the solver's projections remove.
 #include <algorithm>
+#include <cmath>
+#include <cstdlib>
 #include <queue>
 #include <vector>
 
@@ -136,16 +142,25 @@ static void forest_children(int n, const std::vector<int>& parent, std::vector<i
     if (parent[v] >= 0) kids[fill[parent[v]]++] = v;
 }
 
+// One edge off the forest and its stretch.
+struct OffEdge {
+  double stretch;
+  int u, v;
+  double w;
+};
+
 // Total stretch of the edges off a forest: the sum over them of w_e times
 // the resistance of the forest path between their ends, which bounds the
 // condition number of the forest-preconditioned Laplacian.  Forest paths
 // through lowest common ancestors, found offline (Tarjan: a depth-first
-// walk that merges each finished subtree into its parent's set).
+// walk that merges each finished subtree into its parent's set).  With
+// `edges`, every off-forest edge is also listed once with its stretch.
 static double forest_stretch(const DevGraph* g, const std::vector<int>& parent,
-                             const std::vector<double>& pw) {
+                             const std::vector<double>& pw, std::vector<OffEdge>* edges = nullptr) {
   const int n = g->n;
   const std::vector<int>& rp = g->h_rp;
   const std::vector<int>& ci = g->h_ci;
+  const bool weighted = !g->h_w.empty();
   std::vector<int> coff, kids;
   forest_children(n, parent, coff, kids);
   std::vector<int> uf(n), anc(n);
@@ -181,7 +196,10 @@ static double forest_stretch(const DevGraph* g, const std::vector<int>& parent,
         const int u = ci[e];
         if (!done[u] || u == v || parent[u] == v || parent[v] == u) continue;
         const int l = anc[find(u)];
-        stretch += g->h_w[e] * (dist[u] + dist[v] - 2.0 * dist[l]);
+        const double w = weighted ? g->h_w[e] : 1.0;
+        const double se = w * (dist[u] + dist[v] - 2.0 * dist[l]);
+        stretch += se;
+        if (edges) edges->push_back(OffEdge{se, u, v, w});
       }
       stack.pop_back();
       if (parent[v] >= 0) {
@@ -191,6 +209,18 @@ static double forest_stretch(const DevGraph* g, const std::vector<int>& parent,
     }
   }
   return stretch;
+}
+
+// Off-forest edges added back to the forest (the augmentation): the
+// kAugMax of largest stretch, fewer where n x k doubles would pass 512 MB;
+// NVD_TREE_AUG sets the count (0: none).
+constexpr int kAugMax = 256;
+static int aug_count(const DevGraph* g, long n_off) {
+  long k = kAugMax;
+  if (const char* e = std::getenv("NVD_TREE_AUG")) k = std::max(0L, std::strtol(e, nullptr, 10));
+  k = std::min(k, n_off);
+  k = std::min(k, (1L << 26) / std::max(1, g->n));
+  return (int)k;
 }
 
 // host: spanning forest (the breadth-first one on unit weights; on weighted
@@ -211,6 +241,22 @@ static nvd_status build_tree(DevGraph* g) {
       pw.swap(pw2);
       tree_edges = e2;
     }
+  }
+  // the augmentation: the off-forest edges of largest stretch
+  std::vector<OffEdge> aug;
+  const long n_off = (long)g->nnz / 2 - tree_edges;
+  const int k_aug = aug_count(g, n_off);
+  if (k_aug > 0) {
+    forest_stretch(g, parent, pw, &aug);
+    auto larger = [](const OffEdge& a, const OffEdge& b) {
+      if (a.stretch != b.stretch) return a.stretch > b.stretch;
+      return a.u != b.u ? a.u < b.u : a.v < b.v;
+    };
+    if ((long)aug.size() > k_aug) {
+      std::nth_element(aug.begin(), aug.begin() + k_aug, aug.end(), larger);
+      aug.resize(k_aug);
+    }
+    std::sort(aug.begin(), aug.end(), larger);
   }
   // children lists (CSR), then an iterative depth-first Euler tour
   std::vector<int> coff, kids;
@@ -247,6 +293,12 @@ static nvd_status build_tree(DevGraph* g) {
   }
   TreePre* tp = new TreePre();
   tp->n_tree_edges = tree_edges;
+  tp->k_aug = (int)aug.size();
+  for (const OffEdge& a : aug) {
+    tp->aug_u.push_back(a.u);
+    tp->aug_v.push_back(a.v);
+    tp->aug_w.push_back(a.w);
+  }
   nvd_status st = NVD_OK;
   auto al = [&](void** p, size_t bytes) {
     if (st == NVD_OK && hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
@@ -260,6 +312,10 @@ static nvd_status build_tree(DevGraph* g) {
   al((void**)&tp->rbeg, sizeof(int) * n);
   al((void**)&tp->rend, sizeof(int) * n);
   al((void**)&tp->tnode, sizeof(int) * 2 * (size_t)n);
+  if (tp->k_aug > 0) {
+    al((void**)&tp->aug_uv, sizeof(int) * 2 * (size_t)tp->k_aug);
+    al((void**)&tp->aug_st, sizeof(double) * 2 * (size_t)tp->k_aug * kMaxTile);
+  }
   if (st == NVD_OK &&
       (hipMemcpy(tp->tin, tin.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess ||
        hipMemcpy(tp->tout, tout.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess ||
@@ -269,6 +325,14 @@ static nvd_status build_tree(DevGraph* g) {
        hipMemcpy(tp->winv, winv.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess)) {
     set_error("tree preconditioner: upload failed");
     st = NVD_E_DEVICE;
+  }
+  if (st == NVD_OK && tp->k_aug > 0) {
+    std::vector<int> uv(tp->aug_u);
+    uv.insert(uv.end(), tp->aug_v.begin(), tp->aug_v.end());
+    if (hipMemcpy(tp->aug_uv, uv.data(), sizeof(int) * uv.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("tree preconditioner: upload failed");
+      st = NVD_E_DEVICE;
+    }
   }
   if (st != NVD_OK) {
     free_tree(tp);
@@ -280,7 +344,9 @@ static nvd_status build_tree(DevGraph* g) {
 
 void free_tree(TreePre* tp) {
   if (!tp) return;
-  void* ptrs[] = {tp->tin, tp->tout, tp->winv, tp->rbeg, tp->rend, tp->tnode, tp->E, tp->S, tp->part};
+  void* ptrs[] = {tp->tin,  tp->tout, tp->winv, tp->rbeg,   tp->rend,   tp->tnode,
+                  tp->E,    tp->S,    tp->part, tp->aug_uv, tp->aug_st, tp->aug_Y,
+                  tp->aug_Cinv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete tp;
@@ -290,15 +356,21 @@ bool use_tree(const DevGraph* g, uint32_t flags) {
   if (flags & NVD_PRECOND_TREE) return true;
   if (!(flags & NVD_PRECOND_AUTO)) return false;
   // edges off a spanning forest: m - (n - c); each adds at most one PCG
-  // iteration to the tree's exact solve
+  // iteration to the tree's exact solve, and none if the augmentation
+  // takes them all
   const long off = (long)g->nnz / 2 - g->n + g->n_comp;
-  return off * 100 <= (long)g->n;
+  return off * 100 <= (long)g->n || off <= aug_count(g, off);
 }
+
+static nvd_status build_aug(DevGraph* g);
 
 nvd_status ensure_tree(DevGraph* g, int T) {
   if (!g->tree) NVD_TRY(build_tree(g));
   TreePre* tp = g->tree;
-  if (tp->cap_tile >= T) return NVD_OK;
+  if (tp->cap_tile >= T) {
+    if (tp->k_aug > 0 && !tp->aug_Y) NVD_TRY(build_aug(g));
+    return NVD_OK;
+  }
   void* ptrs[] = {tp->E, tp->S, tp->part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -309,6 +381,7 @@ nvd_status ensure_tree(DevGraph* g, int T) {
   NVD_HIP(hipMalloc((void**)&tp->S, sizeof(double) * rows * T));
   NVD_HIP(hipMalloc((void**)&tp->part, sizeof(double) * nchunk * T));
   tp->cap_tile = T;
+  if (tp->k_aug > 0 && !tp->aug_Y) NVD_TRY(build_aug(g));
   return NVD_OK;
 }
 
@@ -488,6 +561,86 @@ static void scan_rows(long rows, int T, const double* E, double* part, double* S
   k_scan_apply<V, TO_Z><<<nchunk, 256, 0, s>>>(rows, T, chunk, E, part, S, tnode, z);
 }
 
+// ---------------------------------------------------------------------------
+// augmentation (Woodbury): z -= Y C^-1 U^T z, with U the signed incidence
+// columns of the k added edges, Y = L_T^+ U and C = W^-1 + U^T Y
+// ---------------------------------------------------------------------------
+// s[f][c] = z[u_f][c] - z[v_f][c]
+template <typename V>
+__global__ void k_aug_s(int T, int k, const int* __restrict__ uv, const V* __restrict__ z,
+                        double* __restrict__ sv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k * T) return;
+  const int f = i / T, c = i % T;
+  sv[(size_t)f * kMaxTile + c] = (double)z[(long)uv[f] * T + c] - (double)z[(long)uv[k + f] * T + c];
+}
+
+// out[i][c] = sum_f A[i][f] B[f][c] for rows i < rows, columns c < T (A
+// row-major with k columns, B with row stride kMaxTile), in a fixed order:
+// B staged in LDS 64 rows at a time, four partial sums per thread.  SUB:
+// out -= (V), else out = (double).  One thread per (row, column).
+template <typename O, bool SUB>
+__global__ __launch_bounds__(256) void k_aug_gemm(long rows, int T, int k, const double* __restrict__ A,
+                                                  const double* __restrict__ B, O* __restrict__ out) {
+  constexpr int FC = 64;
+  __shared__ double bl[FC * kMaxTile];
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  const long i = e / T;
+  const int c = (int)(e % T);
+  const bool live = i < rows;
+  const double* a = A + (live ? i : 0) * (long)k;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int f0 = 0; f0 < k; f0 += FC) {
+    const int fc = min(FC, k - f0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < fc * T; q += 256) bl[(q / T) * kMaxTile + q % T] = B[(size_t)(f0 + q / T) * kMaxTile + q % T];
+    __syncthreads();
+    if (live) {
+      int j = 0;
+      for (; j + 3 < fc; j += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += a[f0 + j + u] * bl[(j + u) * kMaxTile + c];
+      }
+      for (; j < fc; ++j) acc[0] += a[f0 + j] * bl[j * kMaxTile + c];
+    }
+  }
+  if (!live) return;
+  const double v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  if constexpr (SUB)
+    out[e] = (O)((double)out[e] - v);
+  else
+    out[i * kMaxTile + c] = v;
+}
+
+// Set-up helpers: a tile of U's columns f0 .. f0 + T - 1 (zero beyond k),
+// the solved tile into Y's columns, and U^T Y.
+__global__ void k_aug_zero(long len, double* __restrict__ a) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (long)gridDim.x * blockDim.x)
+    a[i] = 0.0;
+}
+__global__ void k_aug_rhs(int T, int f0, int k, const int* __restrict__ uv, double* __restrict__ ut) {
+  const int c = threadIdx.x;
+  if (c >= T || f0 + c >= k) return;
+  ut[(long)uv[f0 + c] * T + c] = 1.0;
+  ut[(long)uv[k + f0 + c] * T + c] = -1.0;
+}
+__global__ void k_aug_store(int n, int T, int f0, int k, const double* __restrict__ yt,
+                            double* __restrict__ Y) {
+  const long tot = (long)n * T;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+    const long v = e / T;
+    const int c = (int)(e % T);
+    if (f0 + c < k) Y[v * k + f0 + c] = yt[e];
+  }
+}
+__global__ void k_aug_gram(int k, const int* __restrict__ uv, const double* __restrict__ Y,
+                           double* __restrict__ G) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k * k) return;
+  const int e = i / k, f = i % k;
+  G[i] = Y[(long)uv[e] * k + f] - Y[(long)uv[k + e] * k + f];
+}
+
 template <typename V>
 static nvd_status tree_solve_t(DevGraph* g, int T, const V* r, V* z, hipStream_t s) {
   TreePre* tp = g->tree;
@@ -499,7 +652,113 @@ static nvd_status tree_solve_t(DevGraph* g, int T, const V* r, V* z, hipStream_t
   k_tour_flow<V><<<std::max(grid, 1), 256, 0, s>>>(n, T, r, tp->tin, tp->tout, tp->rbeg, tp->rend,
                                                    tp->winv, tp->S, tp->E);
   scan_rows<V, true>(rows, T, tp->E, tp->part, nullptr, tp->tnode, z, s);
+  if (tp->aug_Y) {
+    // the augmentation: z -= Y C^-1 U^T z (Woodbury)
+    const int k = tp->k_aug;
+    double* sv = tp->aug_st;
+    double* tv = tp->aug_st + (size_t)k * kMaxTile;
+    const int kt = (k * T + 255) / 256;
+    k_aug_s<V><<<kt, 256, 0, s>>>(T, k, tp->aug_uv, z, sv);
+    k_aug_gemm<double, false><<<kt, 256, 0, s>>>(k, T, k, tp->aug_Cinv, sv, tv);
+    k_aug_gemm<V, true><<<(int)(((long)n * T + 255) / 256), 256, 0, s>>>(n, T, k, tp->aug_Y, tv, z);
+  }
   NVD_HIP(hipGetLastError());
+  return NVD_OK;
+}
+
+// Y = L_T^+ U by tree solves of U's columns, a tile at a time; C = W^-1 +
+// U^T Y on the host, inverted by Cholesky.  If C is not numerically
+// positive definite the augmentation is dropped (plain forest).
+static nvd_status build_aug(DevGraph* g) {
+  TreePre* tp = g->tree;
+  const int n = g->n, k = tp->k_aug, T = tp->cap_tile;
+  const hipStream_t s = nullptr;
+  double *ut = nullptr, *yt = nullptr, *Y = nullptr, *G = nullptr;
+  nvd_status st = NVD_OK;
+  auto al = [&](double** p, size_t count) {
+    if (st == NVD_OK && hipMalloc((void**)p, sizeof(double) * std::max<size_t>(count, 1)) != hipSuccess) {
+      set_error("tree preconditioner: out of device memory (augmentation)");
+      st = NVD_E_NOMEM;
+    }
+  };
+  al(&ut, (size_t)n * T);
+  al(&yt, (size_t)n * T);
+  al(&Y, (size_t)n * k);
+  al(&G, (size_t)k * k);
+  const int grid = (int)std::min<long>(4096, ((long)n * T + 255) / 256);
+  for (int f0 = 0; st == NVD_OK && f0 < k; f0 += T) {
+    k_aug_zero<<<std::max(grid, 1), 256, 0, s>>>((long)n * T, ut);
+    k_aug_rhs<<<1, 64, 0, s>>>(T, f0, k, tp->aug_uv, ut);
+    st = tree_solve_t<double>(g, T, ut, yt, s);
+    if (st == NVD_OK) k_aug_store<<<std::max(grid, 1), 256, 0, s>>>(n, T, f0, k, yt, Y);
+  }
+  std::vector<double> C((size_t)k * k);
+  if (st == NVD_OK) {
+    k_aug_gram<<<(k * k + 255) / 256, 256, 0, s>>>(k, tp->aug_uv, Y, G);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpy(C.data(), G, sizeof(double) * C.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+      set_error("tree preconditioner: augmentation set-up failed");
+      st = NVD_E_DEVICE;
+    }
+  }
+  (void)hipFree(ut);
+  (void)hipFree(yt);
+  (void)hipFree(G);
+  if (st != NVD_OK) {
+    (void)hipFree(Y);
+    return st;
+  }
+  // C = W^-1 + U^T Y, symmetrised; Cholesky C = L L^T; C^-1 column by column
+  for (int e = 0; e < k; ++e) C[(size_t)e * k + e] += 1.0 / tp->aug_w[e];
+  for (int e = 0; e < k; ++e)
+    for (int f = 0; f < e; ++f) {
+      const double m = 0.5 * (C[(size_t)e * k + f] + C[(size_t)f * k + e]);
+      C[(size_t)e * k + f] = C[(size_t)f * k + e] = m;
+    }
+  std::vector<double> L((size_t)k * k, 0.0);
+  bool spd = true;
+  for (int j = 0; j < k && spd; ++j) {
+    double d = C[(size_t)j * k + j];
+    for (int q = 0; q < j; ++q) d -= L[(size_t)j * k + q] * L[(size_t)j * k + q];
+    if (!(d > 0.0) || !std::isfinite(d)) {
+      spd = false;
+      break;
+    }
+    const double ljj = std::sqrt(d);
+    L[(size_t)j * k + j] = ljj;
+    for (int i = j + 1; i < k; ++i) {
+      double a = C[(size_t)i * k + j];
+      for (int q = 0; q < j; ++q) a -= L[(size_t)i * k + q] * L[(size_t)j * k + q];
+      L[(size_t)i * k + j] = a / ljj;
+    }
+  }
+  if (!spd) {
+    (void)hipFree(Y);
+    tp->k_aug = 0;
+    return NVD_OK;
+  }
+  std::vector<double> Cinv((size_t)k * k), col(k);
+  for (int j = 0; j < k; ++j) {
+    for (int i = 0; i < k; ++i) {   // L y = e_j
+      double a = i == j ? 1.0 : 0.0;
+      for (int q = 0; q < i; ++q) a -= L[(size_t)i * k + q] * col[q];
+      col[i] = a / L[(size_t)i * k + i];
+    }
+    for (int i = k - 1; i >= 0; --i) {   // L^T x = y
+      double a = col[i];
+      for (int q = i + 1; q < k; ++q) a -= L[(size_t)q * k + i] * col[q];
+      col[i] = a / L[(size_t)i * k + i];
+    }
+    for (int i = 0; i < k; ++i) Cinv[(size_t)i * k + j] = col[i];
+  }
+  if (hipMalloc((void**)&tp->aug_Cinv, sizeof(double) * Cinv.size()) != hipSuccess ||
+      hipMemcpy(tp->aug_Cinv, Cinv.data(), sizeof(double) * Cinv.size(), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    (void)hipFree(Y);
+    set_error("tree preconditioner: augmentation upload failed");
+    return NVD_E_DEVICE;
+  }
+  tp->aug_Y = Y;
   return NVD_OK;
 }
 

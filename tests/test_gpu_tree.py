@@ -1,9 +1,10 @@
 """GPU parity of the spanning-tree preconditioner (NVD_PRECOND_TREE):
-exact on trees (one CG iteration), a rank-one correction on cycles, and far
-fewer iterations than the Jacobi diagonal on the tree-like graphs of the
-density sweep (on a graph with many edges off a breadth-first tree the
-Jacobi diagonal is the better of the two; there only parity is checked);
-distances against the oracle's exact routes everywhere."""
+exact on trees (one CG iteration), and on a forest augmented with every
+off-forest edge (up to 256 of them, solved with the forest by the Woodbury
+identity), far fewer iterations than the Jacobi diagonal on the tree-like
+graphs of the density sweep (on a graph with many edges off a breadth-first
+tree the Jacobi diagonal is the better of the two; there only parity is
+checked); distances against the oracle's exact routes everywhere."""
 import numpy as np
 import pytest
 
@@ -141,6 +142,61 @@ def test_weighted_graph_takes_the_maximum_weight_forest(precision, rtol, tol):
         [i["iters"] for i in info]
 
 
+def _tree_plus_edges(n, m_extra, seed):
+    rng = np.random.default_rng(seed)
+    t = random_tree(n, rng)
+    xu = rng.integers(0, n, 3 * m_extra)
+    xv = rng.integers(0, n, 3 * m_extra)
+    eu = np.concatenate([t.eu, np.minimum(xu, xv)])
+    ev = np.concatenate([t.ev, np.maximum(xu, xv)])
+    keep = eu != ev
+    eu, ev = eu[keep], ev[keep]
+    _, first = np.unique(eu * n + ev, return_index=True)
+    first = np.sort(first)[: n - 1 + m_extra]      # the tree's edges first, then m_extra others
+    eu, ev = eu[first], ev[first]
+    return Graph(n, eu, ev, rng.lognormal(0.0, 1.0, eu.size)), rng
+
+
+@pytest.mark.parametrize("precision,rtol,tol", PREC)
+def test_augmented_forest_is_exact_with_few_off_edges(monkeypatch, precision, rtol, tol):
+    """120 edges off the forest, all added back: the preconditioner is the
+    exact pseudoinverse, so CG stops after one iteration per solve, as on a
+    tree; without the augmentation it needs many more."""
+    g, rng = _tree_plus_edges(20_000, 120, 21)
+    P, Q = sparse_support_pairs(g.n, 8, 0.05, rng)
+    say("augmented forest exact", precision)
+    ref = oracle.ge_grounded(g.n, g.row_ptr, g.col_idx, g.w, P, Q, sparse=True)["d"]
+    dg = dev_graph(g)
+    d, _, info = dg.distances(P, Q, precision=precision, rtol=rtol, precond="tree")
+    assert rel_err(d.cpu().numpy(), ref).max() <= tol
+    assert all(i["status"] == 0 for i in info)
+    assert max(i["iters"] for i in info) <= (2 if precision == "fp64" else 6), info[0]
+    monkeypatch.setenv("NVD_TREE_AUG", "0")
+    dp = dev_graph(g)
+    d0, _, info0 = dp.distances(P, Q, precision=precision, rtol=rtol, precond="tree")
+    assert rel_err(d0.cpu().numpy(), ref).max() <= tol
+    assert min(i["iters"] for i in info0) > 2 * max(i["iters"] for i in info)
+
+
+def test_augmented_forest_cuts_iterations_on_a_sparse_weighted_graph(monkeypatch):
+    """ER graph of average degree 2 (about 1,500 edges off the forest),
+    lognormal weights: the 256 edges of largest stretch added to the forest
+    cut the iterations; both agree with the oracle."""
+    rng = np.random.default_rng(23)
+    g0, P, Q = density_graph("er", 2)
+    g = g0.with_weights(rng.lognormal(0.0, 2.0, g0.num_edges))
+    say("augmented forest ER d=2")
+    ref = oracle.ge_grounded(g.n, g.row_ptr, g.col_idx, g.w, P, Q)["d"]
+    d, _, info = dev_graph(g).distances(P, Q, precision="fp64", rtol=1e-10, precond="tree")
+    monkeypatch.setenv("NVD_TREE_AUG", "0")
+    d0, _, info0 = dev_graph(g).distances(P, Q, precision="fp64", rtol=1e-10, precond="tree")
+    assert rel_err(d.cpu().numpy(), ref).max() <= 1e-8
+    assert rel_err(d0.cpu().numpy(), ref).max() <= 1e-8
+    its, its0 = sum(i["iters"] for i in info), sum(i["iters"] for i in info0)
+    print("[aug] iterations with / without", its, its0, flush=True)
+    assert its < 0.8 * its0
+
+
 @pytest.mark.parametrize("tile", [1, 2, 4, 8, 16, 32, 64])
 def test_tree_every_tile_width(tile):
     """The tour scans split each chunk over 256/T lanes per column: every
@@ -257,14 +313,15 @@ def test_pairwise_with_tree_preconditioner():
 @pytest.mark.parametrize("model,deg,expect_tree", [("ws", 1, True), ("ba", 2, True), ("er", 2, False),
                                                    ("ws", 4, False)])
 def test_auto_picks_tree_only_when_few_edges_lie_off_it(model, deg, expect_tree):
-    """precond="auto": the forest when m - n + c <= n/100, else the diagonal;
-    the iteration counts show which one ran."""
+    """precond="auto": the forest when m - n + c <= n/100 or when the
+    augmentation takes every off-forest edge (at most 256 here), else the
+    diagonal; the iteration counts show which one ran."""
     g, P, Q = density_graph(model, deg)
     say("tree auto", model, deg)
     dg = dev_graph(g)
     st = dg.stats()
     off = g.num_edges - g.n + st["n_comp"]
-    assert (off * 100 <= g.n) == expect_tree
+    assert (off * 100 <= g.n or off <= 256) == expect_tree
     runs = {}
     for pre in ("jacobi", "tree", "auto"):
         d, _, info = dg.distances(P, Q, precision="fp64", rtol=1e-10, precond=pre)
