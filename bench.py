@@ -46,8 +46,11 @@ def _profile_fields(path):
     return fields
 
 
+# The sources that define the SpMM kernel's device code: the kernel, its
+# device helpers and the device-side types (host-only declarations live
+# elsewhere and do not change the kernel).
 KERNEL_SOURCES = ("paper_2310_11222_amd/csrc/spmm.hip", "paper_2310_11222_amd/csrc/device_common.hpp",
-                  "paper_2310_11222_amd/csrc/nvd_internal.hpp")
+                  "paper_2310_11222_amd/csrc/device_types.hpp")
 
 
 def kernel_source_sha():
