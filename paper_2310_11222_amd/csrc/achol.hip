@@ -237,8 +237,15 @@ __global__ __launch_bounds__(256) void k_am_part(int n, int T, const V* __restri
   const long rows = ((long)n + gridDim.x - 1) / gridDim.x;
   const long lo = (long)blockIdx.x * rows;
   const long hi = min((long)n, lo + rows);
-  double acc = 0.0;
-  for (long i = lo + t / T; i < hi; i += rpb) acc += (double)r[i * T + c];
+  // eight rows in flight per thread, summed in a fixed order
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  long i = lo + t / T;
+  for (; i + 7L * rpb < hi; i += 8L * rpb) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += (double)r[(i + (long)u * rpb) * T + c];
+  }
+  for (int u = 0; i < hi; i += rpb, ++u) a[u & 7] += (double)r[i * T + c];
+  const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   sh[t] = acc;
   __syncthreads();
   for (int h = 128; h >= T; h >>= 1) {
@@ -309,17 +316,17 @@ __device__ __forceinline__ double pull(int lo, int hi, int j, int NL, int col,
 // Forward round, positions [p0, p1): y_u (kept in z) = r_u - mean + pulls
 // from earlier vertices.  WAVE: one wave per vertex, its 64 / T lane
 // sub-groups splitting the list and meeting by shuffles (fixed order);
-// otherwise one 256-thread block per vertex (rounds with long lists), the
-// 256 / T sub-groups meeting in LDS.
-template <typename V, typename C, int T, bool WAVE>
-__global__ __launch_bounds__(256) void k_am_fwd(int p0, int p1, const int* __restrict__ order,
-                                                const int* __restrict__ in_off,
-                                                const int* __restrict__ in_idx,
-                                                const C* __restrict__ in_c, const V* __restrict__ r,
-                                                const int* __restrict__ comp,
-                                                const double* __restrict__ mean, V* __restrict__ z) {
-  constexpr int NL = (WAVE ? 64 : 256) / T;
-  __shared__ double sh[WAVE ? 1 : 256];
+// otherwise one 1024-thread block per vertex (rounds with long lists), its
+// BS / T sub-groups meeting in LDS.
+template <typename V, typename C, int T, bool WAVE, int BS = 256>
+__global__ __launch_bounds__(BS) void k_am_fwd(int p0, int p1, const int* __restrict__ order,
+                                               const int* __restrict__ in_off,
+                                               const int* __restrict__ in_idx,
+                                               const C* __restrict__ in_c, const V* __restrict__ r,
+                                               const int* __restrict__ comp,
+                                               const double* __restrict__ mean, V* __restrict__ z) {
+  constexpr int NL = (WAVE ? 64 : BS) / T;
+  __shared__ double sh[WAVE ? 1 : BS];
   const int t = threadIdx.x;
   const int lt = WAVE ? (t & 63) : t;
   const int p = WAVE ? p0 + blockIdx.x * 4 + (t >> 6) : p0 + blockIdx.x;
@@ -332,7 +339,7 @@ __global__ __launch_bounds__(256) void k_am_fwd(int p0, int p1, const int* __res
   } else {
     sh[t] = acc;
     __syncthreads();
-    for (int h = 128; h >= T; h >>= 1) {
+    for (int h = BS / 2; h >= T; h >>= 1) {
       if (t < h) sh[t] += sh[t + h];
       __syncthreads();
     }
@@ -346,14 +353,14 @@ __global__ __launch_bounds__(256) void k_am_fwd(int p0, int p1, const int* __res
 
 // Backward round, positions [p0, p1): z_v = y_v / W_v + pulls from later
 // vertices (already final); split as in the forward round.
-template <typename V, typename C, int T, bool WAVE>
-__global__ __launch_bounds__(256) void k_am_bwd(int p0, int p1, const int* __restrict__ order,
-                                                const int* __restrict__ out_off,
-                                                const int* __restrict__ out_idx,
-                                                const C* __restrict__ out_c,
-                                                const C* __restrict__ inv_pivot, V* __restrict__ z) {
-  constexpr int NL = (WAVE ? 64 : 256) / T;
-  __shared__ double sh[WAVE ? 1 : 256];
+template <typename V, typename C, int T, bool WAVE, int BS = 256>
+__global__ __launch_bounds__(BS) void k_am_bwd(int p0, int p1, const int* __restrict__ order,
+                                               const int* __restrict__ out_off,
+                                               const int* __restrict__ out_idx,
+                                               const C* __restrict__ out_c,
+                                               const C* __restrict__ inv_pivot, V* __restrict__ z) {
+  constexpr int NL = (WAVE ? 64 : BS) / T;
+  __shared__ double sh[WAVE ? 1 : BS];
   const int t = threadIdx.x;
   const int lt = WAVE ? (t & 63) : t;
   const int p = WAVE ? p0 + blockIdx.x * 4 + (t >> 6) : p0 + blockIdx.x;
@@ -366,7 +373,7 @@ __global__ __launch_bounds__(256) void k_am_bwd(int p0, int p1, const int* __res
   } else {
     sh[t] = acc;
     __syncthreads();
-    for (int h = 128; h >= T; h >>= 1) {
+    for (int h = BS / 2; h >= T; h >>= 1) {
       if (t < h) sh[t] += sh[t + h];
       __syncthreads();
     }
@@ -493,7 +500,10 @@ nvd_status ensure_achol(DevGraph* g) {
   return NVD_OK;
 }
 
-// Rounds whose longest pull list reaches this take a block per vertex.
+// Rounds whose longest pull list reaches this take a 1024-thread block per
+// vertex, so that a hub's list, which grows with every neighbour eliminated
+// before it, is read 16 rows at a time (and the round's time is that of its
+// longest list).
 constexpr int kAmLongList = 256;
 
 template <typename V, int T>
@@ -508,8 +518,8 @@ static void achol_rounds(const DevGraph* g, const V* r, V* z, hipStream_t s) {
     const int p0 = ap->round_off[k], p1 = ap->round_off[k + 1];
     if (p1 <= p0) continue;
     if (ap->fwd_max[k] >= kAmLongList)
-      k_am_fwd<V, C, T, false><<<p1 - p0, 256, 0, s>>>(p0, p1, ap->order, ap->in_off, ap->in_idx, in_c,
-                                                       r, g->comp, ap->mean, z);
+      k_am_fwd<V, C, T, false, 1024><<<p1 - p0, 1024, 0, s>>>(p0, p1, ap->order, ap->in_off, ap->in_idx,
+                                                               in_c, r, g->comp, ap->mean, z);
     else
       k_am_fwd<V, C, T, true><<<(p1 - p0 + 3) / 4, 256, 0, s>>>(p0, p1, ap->order, ap->in_off,
                                                                 ap->in_idx, in_c, r, g->comp, ap->mean, z);
@@ -518,8 +528,8 @@ static void achol_rounds(const DevGraph* g, const V* r, V* z, hipStream_t s) {
     const int p0 = ap->round_off[k], p1 = ap->round_off[k + 1];
     if (p1 <= p0) continue;
     if (ap->bwd_max[k] >= kAmLongList)
-      k_am_bwd<V, C, T, false><<<p1 - p0, 256, 0, s>>>(p0, p1, ap->order, ap->out_off, ap->out_idx,
-                                                       out_c, ip, z);
+      k_am_bwd<V, C, T, false, 1024><<<p1 - p0, 1024, 0, s>>>(p0, p1, ap->order, ap->out_off,
+                                                               ap->out_idx, out_c, ip, z);
     else
       k_am_bwd<V, C, T, true><<<(p1 - p0 + 3) / 4, 256, 0, s>>>(p0, p1, ap->order, ap->out_off,
                                                                 ap->out_idx, out_c, ip, z);
