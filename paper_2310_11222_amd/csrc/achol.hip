@@ -91,22 +91,33 @@ struct HostFactor {
   int remainder = 0;
 };
 
-// Merge repeated neighbours (sum of weights) and drop dead ones.
-void compact(std::vector<Nb>& a, const std::vector<char>& alive) {
-  size_t k = 0;
-  for (size_t i = 0; i < a.size(); ++i)
-    if (alive[a[i].u]) a[k++] = a[i];
-  a.resize(k);
-  if (k < 2) return;
-  std::sort(a.begin(), a.end(), [](const Nb& x, const Nb& y) { return x.u < y.u; });
-  size_t o = 0;
-  for (size_t i = 1; i < a.size(); ++i) {
-    if (a[i].u == a[o].u)
-      a[o].w += a[i].w;
-    else
-      a[++o] = a[i];
+// Merge repeated neighbours (sum of weights) and drop dead ones.  The first
+// `clean` entries are already merged and sorted by neighbour (a previous
+// compaction); only the entries appended since (fill) are sorted, then
+// merged in: O(d + t log t) for t new entries instead of O(d log d), which
+// matters for hubs, whose lists are compacted in almost every round.
+void compact(std::vector<Nb>& a, int& clean, const std::vector<char>& alive) {
+  size_t k = 0, kept = 0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    if (!alive[a[i].u]) continue;
+    if (i < (size_t)clean) ++kept;
+    a[k++] = a[i];
   }
-  a.resize(o + 1);
+  a.resize(k);
+  auto by_u = [](const Nb& x, const Nb& y) { return x.u < y.u; };
+  std::stable_sort(a.begin() + kept, a.end(), by_u);
+  std::inplace_merge(a.begin(), a.begin() + kept, a.end(), by_u);
+  if (k >= 2) {
+    size_t o = 0;
+    for (size_t i = 1; i < a.size(); ++i) {
+      if (a[i].u == a[o].u)
+        a[o].w += a[i].w;
+      else
+        a[++o] = a[i];
+    }
+    a.resize(o + 1);
+  }
+  clean = (int)a.size();
 }
 
 HostFactor factor_graph(const DevGraph* g, int max_rounds) {
@@ -120,6 +131,11 @@ HostFactor factor_graph(const DevGraph* g, int max_rounds) {
     for (int e = rp[v]; e < rp[v + 1]; ++e) adj[v].push_back(Nb{ci[e], weighted ? g->h_w[e] : 1.0});
   }
   std::vector<char> alive(n, 1), blocked(n, 0);
+  // lists that may hold dead or repeated neighbours (every list at first;
+  // then those of eliminated vertices' neighbours and of fill endpoints):
+  // only they are compacted again, the others are already merged and sorted
+  std::vector<char> dirty(n, 1);
+  std::vector<int> clean(n, 0);   // sorted, merged prefix of each list
   std::vector<int> live(n);
   std::iota(live.begin(), live.end(), 0);
   HostFactor f;
@@ -135,7 +151,10 @@ HostFactor factor_graph(const DevGraph* g, int max_rounds) {
     // ascending degree, ties in increasing vertex id
     int dmax = 0;
     for (int v : live) {
-      compact(adj[v], alive);
+      if (dirty[v]) {
+        compact(adj[v], clean[v], alive);
+        dirty[v] = 0;
+      }
       dmax = std::max(dmax, (int)adj[v].size());
     }
     bucket_cnt.assign(dmax + 2, 0);
@@ -189,6 +208,7 @@ HostFactor factor_graph(const DevGraph* g, int max_rounds) {
           adj[a[j].u].push_back(Nb{a[i].u, wn});
         }
       }
+      for (const Nb& nb : a) dirty[nb.u] = 1;   // v dies in their lists; fill lands in some
       alive[v] = 0;
       std::vector<Nb>().swap(a);
     }
@@ -205,7 +225,7 @@ HostFactor factor_graph(const DevGraph* g, int max_rounds) {
   }
   // remainder: the diagonal of the current Schur complement
   for (int v : live) {
-    compact(adj[v], alive);
+    compact(adj[v], clean[v], alive);
     double s = 0.0;
     for (const Nb& nb : adj[v]) s += nb.w;
     f.order.push_back(v);
