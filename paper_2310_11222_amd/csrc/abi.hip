@@ -360,10 +360,17 @@ nvd_status nvd_distances(nvd_graph* h, int32_t k, const double* P, const double*
     sp.nl = tuned_nl(g, o.precision, T);
     st = ensure_workspace(g, T, o.precision == NVD_MIXED);
     const int nb = st == NVD_OK ? small_blocks(g, T, sp) : 0;
-    if (st == NVD_OK && nb > 0)
+    bool done = false;
+    if (st == NVD_OK && nb > 0) {
       st = solve_small(g, T, nb, P + c0, Q + c0, ld, sp, d_out + c0, X ? X + c0 : nullptr, ldx,
                        g->ws->info, s);
-    else if (st == NVD_OK)
+      done = st != NVD_E_UNSUPPORTED;   // a launch too large for the device: multi-kernel path
+      if (!done) {
+        st = NVD_OK;
+        set_error("");
+      }
+    }
+    if (st == NVD_OK && !done)
       st = solve_tile(g, T, P + c0, Q + c0, ld, sp, d_out + c0, X ? X + c0 : nullptr, ldx,
                       g->ws->info, s);
     if (st == NVD_OK) {
