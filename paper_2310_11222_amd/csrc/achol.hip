@@ -48,6 +48,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "device_common.hpp"
@@ -120,6 +121,35 @@ void compact(std::vector<Nb>& a, int& clean, const std::vector<char>& alive) {
   clean = (int)a.size();
 }
 
+// Host threads for the factorization (one for small graphs), and f(lo, hi)
+// on contiguous ranges of [0, n) in parallel.
+int factor_threads(int n) {
+  if (n < (1 << 16)) return 1;
+  const unsigned hw = std::thread::hardware_concurrency();
+  return std::max(1, std::min(hw ? (int)hw : 4, 16));
+}
+template <class F>
+void par_ranges(int n, int nt, F&& f) {
+  if (nt <= 1 || n < 4 * nt) {
+    f(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    const int lo = t * chunk, hi = std::min(n, lo + chunk);
+    if (lo >= hi) break;
+    th.emplace_back([&f, lo, hi]() { f(lo, hi); });
+  }
+  for (auto& x : th) x.join();
+}
+
+// One fill edge of an elimination (a sampled clique edge).
+struct Fill {
+  int a, b;
+  double w;
+};
+
 HostFactor factor_graph(const DevGraph* g, int max_rounds) {
   const int n = g->n;
   const std::vector<int>& rp = g->h_rp;
@@ -144,19 +174,23 @@ HostFactor factor_graph(const DevGraph* g, int max_rounds) {
   f.col_off.push_back(0);
   f.inv_pivot.reserve(n);
   f.round_off.push_back(0);
-  std::vector<int> cand, next_live, bucket_cnt;
-  std::vector<double> pre;
+  std::vector<int> cand, next_live, bucket_cnt, todo;
+  std::vector<std::vector<Nb>> cols;
+  std::vector<std::vector<Fill>> fills;
+  std::vector<double> pivots;
+  const int nt = factor_threads(n);
   for (int r = 0; r < max_rounds && !live.empty(); ++r) {
     // current degrees (merged, live neighbours only), candidates in
     // ascending degree, ties in increasing vertex id
+    todo.clear();
+    for (int v : live)
+      if (dirty[v]) todo.push_back(v);
+    par_ranges((int)todo.size(), nt, [&](int lo, int hi) {   // independent lists
+      for (int i = lo; i < hi; ++i) compact(adj[todo[i]], clean[todo[i]], alive);
+    });
+    for (int v : todo) dirty[v] = 0;
     int dmax = 0;
-    for (int v : live) {
-      if (dirty[v]) {
-        compact(adj[v], clean[v], alive);
-        dirty[v] = 0;
-      }
-      dmax = std::max(dmax, (int)adj[v].size());
-    }
+    for (int v : live) dmax = std::max(dmax, (int)adj[v].size());
     bucket_cnt.assign(dmax + 2, 0);
     for (int v : live) ++bucket_cnt[adj[v].size() + 1];
     for (int d = 0; d <= dmax; ++d) bucket_cnt[d + 1] += bucket_cnt[d];
@@ -174,43 +208,61 @@ HostFactor factor_graph(const DevGraph* g, int max_rounds) {
       for (const Nb& nb : adj[v]) blocked[nb.u] = 1;
     }
     const int round_end = (int)f.order.size();
-    // eliminate the round's vertices
-    for (int p = round_begin; p < round_end; ++p) {
-      const int v = f.order[p];
-      std::vector<Nb>& a = adj[v];
-      const int d = (int)a.size();
-      double W = 0.0;
-      for (const Nb& nb : a) W += nb.w;
-      if (d == 0 || !(W > 0.0)) {
+    // eliminate the round's vertices: each one's factor column and sampled
+    // fill edges in parallel (their lists are disjoint: no two are
+    // adjacent), then recorded and applied in round order
+    const int nr = round_end - round_begin;
+    cols.resize(std::max(nr, 1));
+    fills.resize(std::max(nr, 1));
+    pivots.resize(std::max(nr, 1));
+    par_ranges(nr, nt, [&](int lo, int hi) {
+      std::vector<double> pre;
+      for (int q = lo; q < hi; ++q) {
+        const int v = f.order[round_begin + q];
+        std::vector<Nb>& a = adj[v];
+        const int d = (int)a.size();
+        double W = 0.0;
+        for (const Nb& nb : a) W += nb.w;
+        pivots[q] = (d == 0 || !(W > 0.0)) ? 0.0 : W;
+        cols[q].assign(a.begin(), a.end());   // the column, by neighbour
+        fills[q].clear();
+        if (d >= 2) {
+          std::stable_sort(a.begin(), a.end(), [](const Nb& x, const Nb& y) { return x.w < y.w; });
+          pre.assign(d + 1, 0.0);
+          for (int i = 0; i < d; ++i) pre[i + 1] = pre[i] + a[i].w;
+          for (int i = 0; i + 1 < d; ++i) {
+            const double S = pre[d] - pre[i + 1];            // weights after i
+            const double t = pre[i + 1] + draw((uint64_t)v, (uint64_t)i) * S;
+            // the later neighbour j whose cumulative range holds t
+            int j = (int)(std::upper_bound(pre.begin() + i + 2, pre.begin() + d + 1, t) - pre.begin()) - 1;
+            if (j <= i) j = i + 1;
+            if (j >= d) j = d - 1;
+            fills[q].push_back(Fill{a[i].u, a[j].u, a[i].w * S / W});
+          }
+        }
+      }
+    });
+    for (int q = 0; q < nr; ++q) {
+      const int v = f.order[round_begin + q];
+      const double W = pivots[q];
+      if (W == 0.0) {
         f.inv_pivot.push_back(0.0);   // last vertex of its component: the ground
         ++f.grounds;
       } else {
         f.inv_pivot.push_back(1.0 / W);
       }
-      for (const Nb& nb : a) {
+      for (const Nb& nb : cols[q]) {
         f.col_idx.push_back(nb.u);
-        f.col_c.push_back(nb.w / W);
+        f.col_c.push_back(W == 0.0 ? nb.w : nb.w / W);
+        dirty[nb.u] = 1;   // v dies in their lists; fill lands in some
       }
       f.col_off.push_back((int)f.col_idx.size());
-      if (d >= 2) {
-        std::stable_sort(a.begin(), a.end(), [](const Nb& x, const Nb& y) { return x.w < y.w; });
-        pre.assign(d + 1, 0.0);
-        for (int i = 0; i < d; ++i) pre[i + 1] = pre[i] + a[i].w;
-        for (int i = 0; i + 1 < d; ++i) {
-          const double S = pre[d] - pre[i + 1];            // weights after i
-          const double t = pre[i + 1] + draw((uint64_t)v, (uint64_t)i) * S;
-          // the later neighbour j whose cumulative range holds t
-          int j = (int)(std::upper_bound(pre.begin() + i + 2, pre.begin() + d + 1, t) - pre.begin()) - 1;
-          if (j <= i) j = i + 1;
-          if (j >= d) j = d - 1;
-          const double wn = a[i].w * S / W;
-          adj[a[i].u].push_back(Nb{a[j].u, wn});
-          adj[a[j].u].push_back(Nb{a[i].u, wn});
-        }
+      for (const Fill& e : fills[q]) {
+        adj[e.a].push_back(Nb{e.b, e.w});
+        adj[e.b].push_back(Nb{e.a, e.w});
       }
-      for (const Nb& nb : a) dirty[nb.u] = 1;   // v dies in their lists; fill lands in some
       alive[v] = 0;
-      std::vector<Nb>().swap(a);
+      std::vector<Nb>().swap(adj[v]);
     }
     for (int p = round_begin; p < round_end; ++p) blocked[f.order[p]] = 0;
     for (int v : live) {
