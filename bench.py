@@ -228,7 +228,9 @@ def bench_spmv(calib_copy=False, g=None):
     """The reference SpMV loads for the HBM claim: Y = L X on the 10^7-node
     power-law configuration-model graph (unit weights), k = 1 and 16 columns,
     FP32 and FP64, 100 back-to-back launches each (time per launch from HIP
-    events around the 100).  Algorithmic bytes: 4 nnz + 4 (n+1) + 2 k s n."""
+    events around the 100).  Algorithmic bytes: 4 nnz + 4 (n+1) + 2 k s n.
+    k = 1 runs the apply by column slices (the default at this size) and,
+    for comparison, the row-wise apply (NVD_SLICE=0)."""
     import numpy as np
     import torch
     import paper_2310_11222_amd as nvd
@@ -248,8 +250,11 @@ def bench_spmv(calib_copy=False, g=None):
     gen = torch.Generator(device="cuda")
     gen.manual_seed(5)
     rows = []
-    for k, dt, name in ((1, torch.float32, "f32"), (1, torch.float64, "f64"),
-                        (16, torch.float32, "f32"), (16, torch.float64, "f64")):
+    for k, dt, name, path in ((1, torch.float32, "f32", "sliced"), (1, torch.float64, "f64", "sliced"),
+                              (1, torch.float32, "f32", "row-wise"), (1, torch.float64, "f64", "row-wise"),
+                              (16, torch.float32, "f32", "row-wise"), (16, torch.float64, "f64", "row-wise")):
+        if k == 1 and path == "row-wise":
+            os.environ["NVD_SLICE"] = "0"
         X = torch.rand(g.n, k, dtype=dt, device="cuda", generator=gen)
         Y = torch.empty_like(X)
         for _ in range(5):
@@ -264,7 +269,8 @@ def bench_spmv(calib_copy=False, g=None):
         b.synchronize()
         us = a.elapsed_time(b) / 100 * 1e3
         alg = 4.0 * g.nnz + 4.0 * (g.n + 1) + 2.0 * k * X.element_size() * g.n
-        rows.append({"k": k, "dtype": name, "us_per_launch": round(us, 1),
+        os.environ.pop("NVD_SLICE", None)
+        rows.append({"k": k, "dtype": name, "path": path, "us_per_launch": round(us, 1),
                      "algorithmic_bytes": alg, "achieved_gbs": round(alg / us / 1e3, 1),
                      "frac": round(alg / us / 1e3 / HBM_PEAK_GBS, 4)})
         del X, Y
@@ -272,6 +278,37 @@ def bench_spmv(calib_copy=False, g=None):
     res = {"workload": "config_model_n1e7_unit_laplacian_apply", "n": g.n, "nnz": g.nnz,
            "launches": rows, "traffic_k1_f32": load_spmv_traffic()}
     log("spmv: " + json.dumps(res))
+    return res
+
+
+def bench_single_pair(dg, P, Q, rtol, golden, reps=3):
+    """One distance at a time on the 10^7-node graph (the paper's per-distance
+    setting, Table 2): pair 0 of the headline, mixed precision, tile of one
+    column, with the apply by column slices (default at this size) and with
+    the row-wise apply (NVD_SLICE=0).  The first sliced call builds the
+    slices (its time is reported apart)."""
+    import numpy as np
+    import torch
+    p, q = P[:, :1].contiguous(), Q[:, :1].contiguous()
+    res = {"workload": "cm_pl2.5_n1e7_pair0", "precision": "mixed", "tile": 1}
+    for path in ("sliced", "row-wise"):
+        if path == "row-wise":
+            os.environ["NVD_SLICE"] = "0"
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d, _, info = dg.distances(p, q, precision="mixed", rtol=rtol, tile_k=1)
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            d, _, info = dg.distances(p, q, precision="mixed", rtol=rtol, tile_k=1)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        os.environ.pop("NVD_SLICE", None)
+        err = None if golden is None else float(abs(d.cpu().numpy()[0] - golden[0]) / golden[0])
+        res[path] = {"ms_per_distance": round(ms, 2), "first_call_ms": round(first * 1e3, 1),
+                     "iters": info[0]["iters"], "rel_err_vs_oracle": err}
+    log("single pair: " + json.dumps(res))
     return res
 
 
@@ -650,6 +687,7 @@ def main():
                "seconds_measured": round(cb["seconds_measured"], 1)}
         log(f"cpu oracle {cb['rate']:.5f} distances/s ({cb['seconds_measured']:.1f}s measured)")
 
+    single = None if (args.no_legs or args.no_spmv) else bench_single_pair(dg, P, Q, rtol, golden)
     small = None if (args.no_legs or args.no_small) else {"c1_latency": bench_c1(),
                                                           "c4_forward_adjoint": bench_c4()}
     spmv = None
@@ -690,7 +728,7 @@ def main():
                       "ms_per_step": round(t64 * 1e3, 3)},
         "accuracy": acc,
         "legs": {"small": small, "c2": c2, "batched": batched, "density_sweep": density,
-                 "tree_like_1e6": tree_large, "spmv_reference": spmv},
+                 "tree_like_1e6": tree_large, "spmv_reference": spmv, "single_pair_1e7": single},
         "iters_mean": float(np.mean(iters_mixed)),
         "refine_mean": float(np.mean(refine)),
         "setup_s": round(setup_s, 3),

@@ -297,7 +297,7 @@ nvd_status nvd_laplacian_apply(nvd_graph* h, int32_t dtype, int32_t k, const voi
     sc.y = static_cast<char*>(Y) + c0 * es;
     sc.ldy = ldy;
     sc.epi = EPI_PLAIN;
-    NVD_TRY(launch_spmm(sc, g->ws->red, as_stream(stream)));
+    NVD_TRY(launch_apply(sc, g->ws->red, as_stream(stream)));
     c0 += T;
   }
   return NVD_OK;
@@ -455,6 +455,8 @@ nvd_status nvd_graph_set_weights(nvd_graph* h, const double* w, void* stream) {
   if (g->achol) g->bytes -= g->achol->bytes;
   free_achol(g->achol);
   g->achol = nullptr;
+  // the slices of the one-column apply hold copies of the weights
+  free_slices(g);
   g->h_w.resize(std::max(g->nnz, 1));
   if (hipMemcpy(g->h_w.data(), g->w64, sizeof(double) * g->nnz, hipMemcpyDeviceToHost) != hipSuccess) {
     set_error("nvd_graph_set_weights: copying the weights back failed");

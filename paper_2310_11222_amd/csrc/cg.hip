@@ -854,7 +854,7 @@ static nvd_status cg_loop(DevGraph* g, Workspace* ws, int T, V* x, V* r, V* p, V
     const int todo = std::min(chunk, max_iter - done);
     ids.clear();
     for (int it = 0; it < todo; ++it) {
-      NVD_TRY(launch_spmm(sc, ws->red, s));
+      NVD_TRY(launch_apply(sc, ws->red, s));
       ids.push_back(prof_last_id());
       int pid = prof_begin(s, sizeof(V) == 8 ? PK_UPD64 : PK_UPD32, upd_bytes);
       if (sp.tree) {
@@ -965,7 +965,7 @@ static nvd_status enqueue_tune_iteration(DevGraph* g, Workspace* ws, int T, int 
   sc.ldy = T;
   sc.cs = tcs;
   sc.epi = EPI_PLAIN;
-  NVD_TRY(launch_spmm(sc, ws->red, s));
+  NVD_TRY(launch_apply(sc, ws->red, s));
   NVD_TILE_SWITCH(T, (k_update<V, TT><<<reduce_grid(cap / Vec16<V>::N), kBS, 0, s>>>(g->n, cap, r, q, invd, 1.0,
                                                             0x7fffffff, tcs, ws->red)));
   NVD_TILE_SWITCH(T, (k_direction<V, TT><<<sgrid, kBS, 0, s>>>(g->n, cap, x, p, r, invd, tcs)));
@@ -1111,7 +1111,7 @@ nvd_status solve_tile_ws(DevGraph* g, Workspace* ws, int T, const double* P, con
       MeanSrc mx{};
       NVD_TRY(mean_into(g, ws, T, ProjSrc{ws->x64, T, nullptr, 0}, &mx, s));
       NVD_TILE_SWITCH(T, (k_xfinal<TT><<<grid, kBS, 0, s>>>(n, ws->x64, mx, nullptr, 0)));
-      NVD_TRY(launch_spmm(resid, ws->red, s));
+      NVD_TRY(launch_apply(resid, ws->red, s));
       k_check<<<1, 64, 0, s>>>(T, rtol2, ws->cs);
       NVD_HIP(hipGetLastError());
       int no = 0;
@@ -1131,7 +1131,7 @@ nvd_status solve_tile_ws(DevGraph* g, Workspace* ws, int T, const double* P, con
   if (!mixed) {
     if (have_x) {
       // r = delta_bar - L x0, then CG from there
-      NVD_TRY(launch_spmm(resid, ws->red, s));
+      NVD_TRY(launch_apply(resid, ws->red, s));
       NVD_TILE_SWITCH(T, (k_restart<TT><<<grid, kBS, 0, s>>>(n, cap, ws->r64, ws->p64, ws->q64,
                                                              g->invd64, ws->cs, ws->red)));
       NVD_HIP(hipGetLastError());
@@ -1158,7 +1158,7 @@ nvd_status solve_tile_ws(DevGraph* g, Workspace* ws, int T, const double* P, con
       const double* src = ws->b64;
       if (!first) {
         // (a7) FP64 outer residual r = delta_bar - L x, projected
-        NVD_TRY(launch_spmm(resid, ws->red, s));
+        NVD_TRY(launch_apply(resid, ws->red, s));
         resid_current = true;
         if (connected) {
           mr.n = n;
@@ -1202,7 +1202,7 @@ nvd_status solve_tile_ws(DevGraph* g, Workspace* ws, int T, const double* P, con
     // with the poll that ended the loop, else a poll of its own)
     if (!polled) NVD_TRY(poll(ws, s, nullptr, nullptr, &pw));
     if (pw.n_fb > 0) {
-      NVD_TRY(launch_spmm(resid, ws->red, s));
+      NVD_TRY(launch_apply(resid, ws->red, s));
       k_fp64_open<<<1, 64, 0, s>>>(T, ws->cs);
       NVD_TILE_SWITCH(T, (k_restart<TT><<<grid, kBS, 0, s>>>(n, cap, ws->r64, ws->p64, ws->q64,
                                                              g->invd64, ws->cs, ws->red)));
@@ -1219,7 +1219,7 @@ nvd_status solve_tile_ws(DevGraph* g, Workspace* ws, int T, const double* P, con
       MeanSrc mx{};
       NVD_TRY(mean_into(g, ws, T, ProjSrc{ws->x64, T, nullptr, 0}, &mx, s));
       NVD_TILE_SWITCH(T, (k_xfinal<TT><<<grid, kBS, 0, s>>>(n, ws->x64, mx, nullptr, 0)));
-      NVD_TRY(launch_spmm(resid, ws->red, s));
+      NVD_TRY(launch_apply(resid, ws->red, s));
     }
   }
   // (a8) quadratic form, distances, per-pair info; copy x out

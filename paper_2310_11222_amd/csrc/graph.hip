@@ -527,6 +527,7 @@ nvd_status graph_destroy(DevGraph* g) {
   if (g->ws) free_workspace(g->ws);
   free_tree(g->tree);
   free_achol(g->achol);
+  free_slices(g);
   if (g->heavy) (void)hipFree(g->heavy);
   free_graph_arrays(g);
   delete g;

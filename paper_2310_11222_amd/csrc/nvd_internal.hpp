@@ -72,6 +72,8 @@ struct AcholPre {
   int64_t bytes = 0;
 };
 
+struct SliceGraph;   // column slices of the one-column apply (slice.hip)
+
 struct DevGraph {
   int n = 0;
   int nnz = 0;                 // internal nnz (self-loops removed)
@@ -110,6 +112,8 @@ struct DevGraph {
   int n_heavy = -1;            // (built when first needed, longest first; -1: not yet)
   int heavy_base = 0;          // degree threshold the list was built for
   std::vector<int> heavy_deg_desc;  // host: their degrees
+  SliceGraph* slices = nullptr; // built when the sliced apply is first needed
+  int slice_state = 0;          // -1: build failed, use the row-wise apply
 };
 
 struct Workspace {
@@ -177,6 +181,10 @@ struct SpmmCall {
   int grid;                 // short-row blocks (0 = auto)
 };
 nvd_status launch_spmm(const SpmmCall& c, const GridRed& red, hipStream_t s);
+// The apply the solvers and nvd_laplacian_apply use: one column (T = 1) on a
+// large graph by XCD-pinned column slices (slice.hip), else launch_spmm.
+nvd_status launch_apply(const SpmmCall& c, const GridRed& red, hipStream_t s);
+void free_slices(DevGraph* g);
 
 struct SolveParams {
   int precision;            // NVD_FP64 or NVD_MIXED

@@ -88,3 +88,28 @@ def test_configuration_model_1e7_16_pairs():
     e = rel_err(d.cpu().numpy(), ref)
     assert e.max() <= 1e-6, e.max()
     assert all(i["status"] == 0 for i in info)
+    # one column at a time: at 1e7 nodes this is the apply by XCD-pinned
+    # column slices (built on the first such call)
+    b0 = dg.stats()["device_bytes"]
+    d1, _, info1 = dg.distances(P[:, :2], Q[:, :2], precision="mixed", rtol=w.rtol, tile_k=1)
+    assert dg.stats()["device_bytes"] > b0
+    e1 = rel_err(d1.cpu().numpy(), ref[:2])
+    assert e1.max() <= 1e-6, e1.max()
+    assert all(i["status"] == 0 for i in info1)
+    # the sliced apply itself, on sampled rows (the hubs among them) against
+    # the row sums of the definition, FP64 and FP32
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(g.n)
+    rows = np.concatenate([rng.choice(g.n, 3000, replace=False),
+                           np.argsort(np.diff(g.row_ptr))[-20:]])
+    y64 = dg.laplacian_apply(torch.as_tensor(x).cuda()).cpu().numpy().ravel()
+    y32 = dg.laplacian_apply(torch.as_tensor(x).float().cuda()).cpu().numpy().ravel()
+    x32 = x.astype(np.float32).astype(np.float64)
+    for i in rows:
+        nb = g.col_idx[g.row_ptr[i]:g.row_ptr[i + 1]]
+        want = np.sum(x[i] - x[nb])
+        scale = np.sum(np.abs(x[i]) + np.abs(x[nb]))
+        assert abs(y64[i] - want) <= 1e-13 * scale, i
+        want32 = np.sum(x32[i] - x32[nb])
+        scale32 = np.sum(np.abs(x32[i]) + np.abs(x32[nb]))
+        assert abs(y32[i] - want32) <= 2e-6 * scale32, i
