@@ -1,6 +1,6 @@
 // Laplacian apply of one right-hand-side column (T = 1) on large graphs, by
-// column slices pinned to XCDs.  Same operator and edge-difference form as
-// k_spmm (the paper's section 3.1 L = D - A):
+// column slices pinned to XCDs.  Same operator as k_spmm (the paper's
+// section 3.1 L = D - A):
 //   (L x)_v = sum_u w_vu (x_v - x_u).
 //
 // On a large random graph a one-column apply is bound by its neighbour
@@ -8,18 +8,25 @@
 // lines of x do not stay in an XCD's 4 MB L2.  Here the columns (nodes) are
 // cut into S = 8m slices of at most kSlNodes nodes, so that one slice of x
 // fits in one XCD's L2, and the rows into chunks of kSlRows rows:
-//  * slice pass: block b works on slice s = 8r + (b mod 8) of chunk c, with
-//    the blocks of round r first.  The hardware deals consecutive blocks to
-//    the 8 XCDs round-robin, so every gather of a block hits the slice its
-//    XCD holds.  For every row of the chunk with neighbours in the slice (an
-//    "item") it writes one partial sum  sum_{u in slice} w_vu (x_v - x_u).
-//    Items of at most kSlLongItem neighbours take one lane each (4 items per
-//    thread, their neighbour lists contiguous, offsets from a block scan);
-//    longer items take one wave each.
+//  * slice pass: block b works on slice s = 8r + (b mod 8) of kSlGroup
+//    consecutive chunks, with the blocks of round r first.  The hardware
+//    deals consecutive blocks to the 8 XCDs round-robin, so every gather of a
+//    block hits the slice its XCD holds.  For every row of a chunk with
+//    neighbours in the slice (an
+//    "item") it writes one partial sum: in FP64, sum_{u in slice} w_vu (x_v - x_u)
+//    (the edge-difference form); in FP32, sum_{u in slice} w_vu x_u
+//    accumulated in FP64 (x_v is then not read by every slice: at 32 slices
+//    those reads were three quarters of the pass's traffic).  Items of at
+//    most kSlLongItem neighbours take one lane each (4 items per thread,
+//    their neighbour lists contiguous, offsets from a block scan); longer
+//    items take one wave each.
 //  * combine: block per chunk; the partials of each slice are added into an
 //    LDS row accumulator, slice after slice (a row has at most one item per
-//    slice), then the epilogue of the apply (store, CG dot p^T q, or the
-//    FP64 residual r = b - L x and its dots) as in k_spmm.
+//    slice), then (FP32) y_v = d_v x_v - sum in FP64, d_v the FP64 sum of
+//    the row's FP32 weights, rounded once to FP32 -- at least as accurate
+//    as the FP32 edge-difference sum -- and the epilogue of the apply
+//    (store, CG dot p^T q, or the FP64 residual r = b - L x and its dots) as
+//    in k_spmm.
 // Every sum is taken in a fixed order, so results repeat bit for bit.  The
 // slice structure is built on the host from the graph's CSR the first time
 // it is needed and kept with the graph.
@@ -29,6 +36,7 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "device_common.hpp"
@@ -38,6 +46,7 @@ namespace nvd {
 
 constexpr int kSlRows = 2048;        // rows per chunk (LDS accumulator)
 constexpr int kSlLongItem = 32;      // neighbours above which an item takes a wave
+constexpr int kSlGroup = 8;          // chunks of one slice per block of the slice pass
 constexpr int kSlNodes = 327680;     // nodes per slice: 2.5 MB of FP64 x
 constexpr int kSlMinN = 1 << 22;     // graphs this large use the slices by default
 
@@ -62,8 +71,9 @@ struct SliceGraph {
   int* col_l = nullptr;
   float* w32_l = nullptr;
   double* w64_l = nullptr;
-  double* part_s = nullptr;   // one partial per item (FP64 or FP32 in place)
+  double* part_s = nullptr;   // one FP64 partial per item
   double* part_l = nullptr;
+  double* dw32 = nullptr;     // weighted graphs: FP64 sum of each row's FP32 weights
   int64_t bytes = 0;
 };
 
@@ -81,8 +91,9 @@ struct SliceArgs {
   const long* lg_ent;
   const int* col_l;
   const void* w_l;
-  void* part_s;
-  void* part_l;
+  double* part_s;
+  double* part_l;
+  const double* dw;  // FP32 apply: d_v (sum of the row's FP32 weights, in FP64)
   const int* gate;   // EPI_CG: the tile's active count; nothing to do when 0
 };
 
@@ -97,27 +108,49 @@ struct SliceOut {
   ColState* cs;
 };
 
-template <typename V, bool UNIT>
+// DIFF: the edge-difference partial (FP64); else sum w x_u in FP64 (FP32).
+template <typename V, bool UNIT, bool DIFF>
 __global__ __launch_bounds__(kBS) void k_slice_pass(SliceArgs a, const V* __restrict__ x, long ldx) {
+  using A = typename std::conditional<DIFF, V, double>::type;
   __shared__ int wsum[kBS / 64];
+  __shared__ long bnd[kSlGroup + 1];
+  __shared__ long bndl[kSlGroup + 1];
   if (a.gate && *a.gate == 0) return;
-  const int per_round = 8 * a.nch;
+  // block -> (slice s, chunks c0 .. c0+cn-1); consecutive blocks go to the
+  // 8 XCDs in turn, and the blocks of one round cover slices 8r .. 8r+7
+  const int ngrp = (a.nch + kSlGroup - 1) / kSlGroup;
+  const int per_round = 8 * ngrp;
   const int r = (int)blockIdx.x / per_round;
   const int idx = (int)blockIdx.x - r * per_round;
   const int s = r * 8 + (idx & 7);
-  const int c = idx >> 3;
-  const long k = (long)s * a.nch + c;
-  const long base_row = (long)c * kSlRows;
+  const int c0 = (idx >> 3) * kSlGroup;
+  const int cn = min(kSlGroup, a.nch - c0);
+  const long k = (long)s * a.nch + c0;
+  // the items (and neighbours) of consecutive chunks of one slice are
+  // contiguous: the block walks them as one range
+  if ((int)threadIdx.x <= cn) {
+    bnd[threadIdx.x] = a.it_off[k + threadIdx.x];
+    bndl[threadIdx.x] = a.lg_off[k + threadIdx.x];
+  }
+  __syncthreads();
   const V* ws = static_cast<const V*>(a.w_s);
   const V* wl = static_cast<const V*>(a.w_l);
-  V* part_s = static_cast<V*>(a.part_s);
-  V* part_l = static_cast<V*>(a.part_l);
+  A* part_s = reinterpret_cast<A*>(a.part_s);
+  A* part_l = reinterpret_cast<A*>(a.part_l);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const long i0 = a.it_off[k], i1 = a.it_off[k + 1];
+  const long i0 = bnd[0], i1 = bnd[cn];
   long ebase = a.es_off[k];
   for (long tile = i0; tile < i1; tile += 4 * kBS) {
     const long my = tile + 4 * t;
     const bool has = my < i1;
+    // a thread's 4 items lie in one chunk (every chunk's range is a
+    // multiple of 4 items)
+    long base_row = 0;
+    if constexpr (DIFF) {
+      int g = 0;
+      while (g + 1 < cn && bnd[g + 1] <= my) ++g;
+      base_row = (long)(c0 + g) * kSlRows;
+    }
     // 4 items per thread: lrow and count as one 8- and one 4-byte load
     const uint32_t cw = has ? *reinterpret_cast<const uint32_t*>(a.it_cnt + my) : 0u;
     const uint2 lw = has ? *reinterpret_cast<const uint2*>(a.it_lrow + my) : make_uint2(0u, 0u);
@@ -143,12 +176,15 @@ __global__ __launch_bounds__(kBS) void k_slice_pass(SliceArgs a, const V* __rest
     __syncthreads();
     const long e0 = ebase + wpre + incl - tot;
     ebase += btot;
-    V xi[4];
+    V xi[4] = {(V)0, (V)0, (V)0, (V)0};
+    if constexpr (DIFF) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) xi[j] = cnt[j] > 0 ? x[(base_row + lr[j]) * ldx] : (V)0;
+      for (int j = 0; j < 4; ++j) xi[j] = cnt[j] > 0 ? x[(base_row + lr[j]) * ldx] : (V)0;
+    }
     const int c1 = cnt[0], c2 = c1 + cnt[1], c3 = c2 + cnt[2];
-    V acc[4] = {(V)0, (V)0, (V)0, (V)0};
-    constexpr int EU = 4;
+    A acc[4] = {(A)0, (A)0, (A)0, (A)0};
+    // neighbours in flight per thread (FP64 keeps 4: its registers bound occupancy)
+    constexpr int EU = sizeof(V) == 8 ? 4 : 8;
     for (int q0 = 0; q0 < tot; q0 += EU) {
       int cc[EU];
       V wt[EU];
@@ -170,8 +206,13 @@ __global__ __launch_bounds__(kBS) void k_slice_pass(SliceArgs a, const V* __rest
         if (q < tot) {
           // item j of neighbour q: the counts' running sums c1 <= c2 <= c3
           const int j = q < c1 ? 0 : (q < c2 ? 1 : (q < c3 ? 2 : 3));
-          const V xo = j == 0 ? xi[0] : (j == 1 ? xi[1] : (j == 2 ? xi[2] : xi[3]));
-          const V d = wt[u] * (xo - xv[u]);
+          A d;
+          if constexpr (DIFF) {
+            const V xo = j == 0 ? xi[0] : (j == 1 ? xi[1] : (j == 2 ? xi[2] : xi[3]));
+            d = wt[u] * (xo - xv[u]);
+          } else {
+            d = (A)wt[u] * (A)xv[u];
+          }
           if (j == 0)
             acc[0] += d;
           else if (j == 1)
@@ -189,16 +230,25 @@ __global__ __launch_bounds__(kBS) void k_slice_pass(SliceArgs a, const V* __rest
     }
   }
   // long items: one wave each, lanes over the neighbours, fixed-order sum
-  const long l0 = a.lg_off[k], l1 = a.lg_off[k + 1];
+  const long l0 = bndl[0], l1 = bndl[cn];
   for (long q = l0 + wave; q < l1; q += kBS / 64) {
-    const long row = base_row + a.lg_lrow[q];
+    long row = 0;
+    if constexpr (DIFF) {
+      int g = 0;
+      while (g + 1 < cn && bndl[g + 1] <= q) ++g;
+      row = (long)(c0 + g) * kSlRows + a.lg_lrow[q];
+    }
     const int cnt = a.lg_cnt[q];
     const long e = a.lg_ent[q];
-    const V xr = x[row * ldx];
-    V sum = (V)0;
+    const V xr = DIFF ? x[row * ldx] : (V)0;
+    A sum = (A)0;
     for (int j = lane; j < cnt; j += 64) {
       const V wt = UNIT ? (V)1 : wl[e + j];
-      sum += wt * (xr - x[(long)a.col_l[e + j] * ldx]);
+      const V xu = x[(long)a.col_l[e + j] * ldx];
+      if constexpr (DIFF)
+        sum += wt * (xr - xu);
+      else
+        sum += (A)wt * (A)xu;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
@@ -206,24 +256,25 @@ __global__ __launch_bounds__(kBS) void k_slice_pass(SliceArgs a, const V* __rest
   }
 }
 
-template <typename V, int EPI>
+template <typename V, int EPI, bool DIFF>
 __global__ __launch_bounds__(kBS) void k_slice_combine(SliceArgs a, SliceOut<V> o, GridRed red) {
+  using A = typename std::conditional<DIFF, V, double>::type;
   constexpr int ND = EPI == EPI_CG ? 1 : (EPI == EPI_RESID ? 5 : 0);
   constexpr int NDA = ND > 0 ? ND : 1;
-  __shared__ V acc[kSlRows + 1];
+  __shared__ A acc[kSlRows + 1];
   __shared__ double sh_red[ND > 0 ? ND * kBS : 1];
   __shared__ double vals[NDA];
   if constexpr (EPI == EPI_CG) {
     if (o.cs->n_active == 0) return;
   }
   const int t = threadIdx.x;
-  const V* part_s = static_cast<const V*>(a.part_s);
-  const V* part_l = static_cast<const V*>(a.part_l);
+  const A* part_s = reinterpret_cast<const A*>(a.part_s);
+  const A* part_l = reinterpret_cast<const A*>(a.part_l);
   double dacc[NDA][1];
 #pragma unroll
   for (int d = 0; d < NDA; ++d) dacc[d][0] = 0.0;
   for (int c = blockIdx.x; c < a.nch; c += gridDim.x) {
-    for (int i = t; i <= kSlRows; i += kBS) acc[i] = (V)0;
+    for (int i = t; i <= kSlRows; i += kBS) acc[i] = (A)0;
     __syncthreads();
     for (int s = 0; s < a.S; ++s) {
       const long k = (long)s * a.nch + c;
@@ -243,7 +294,11 @@ __global__ __launch_bounds__(kBS) void k_slice_combine(SliceArgs a, SliceOut<V> 
     for (int i = t; i < kSlRows; i += kBS) {
       const long row = (long)c * kSlRows + i;
       if (row >= a.n) break;
-      const V yv = acc[i];
+      V yv;
+      if constexpr (DIFF)
+        yv = acc[i];
+      else
+        yv = (V)((double)o.x[row * o.ldx] * a.dw[row] - acc[i]);
       if constexpr (EPI == EPI_PLAIN) {
         o.y[row * o.ldy] = yv;
       } else if constexpr (EPI == EPI_CG) {
@@ -303,7 +358,7 @@ void free_slices(DevGraph* g) {
   (void)hipDeviceSynchronize();
   void* ps[] = {sg->it_off, sg->es_off, sg->it_lrow, sg->it_cnt, sg->col_s, sg->w32_s, sg->w64_s,
                 sg->lg_off, sg->lg_lrow, sg->lg_cnt, sg->lg_ent, sg->col_l, sg->w32_l, sg->w64_l,
-                sg->part_s, sg->part_l};
+                sg->part_s, sg->part_l, sg->dw32};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   g->bytes -= sg->bytes;
@@ -465,6 +520,12 @@ static nvd_status build_slices(DevGraph* g) {
             up(&sg->lg_lrow, lg_lrow, sg->bytes) && up(&sg->lg_cnt, lg_cnt, sg->bytes) &&
             up(&sg->lg_ent, lg_ent, sg->bytes) && up(&sg->col_l, col_l, sg->bytes);
   if (ok && wtd) {
+    std::vector<double> dw(n, 0.0);
+    for (long i = 0; i < n; ++i)
+      for (long e = rp[i]; e < rp[i + 1]; ++e) dw[i] += (double)(float)hw[e];
+    ok = up(&sg->dw32, dw, sg->bytes);
+  }
+  if (ok && wtd) {
     std::vector<float> f_s(w_s.size()), f_l(w_l.size());
     for (size_t j = 0; j < w_s.size(); ++j) f_s[j] = (float)w_s[j];
     for (size_t j = 0; j < w_l.size(); ++j) f_l[j] = (float)w_l[j];
@@ -539,6 +600,7 @@ static nvd_status launch_sliced(const SpmmCall& c, const GridRed& red, hipStream
   }
   a.part_s = sg->part_s;
   a.part_l = sg->part_l;
+  a.dw = unit ? g->deg64 : sg->dw32;
   a.gate = c.epi == EPI_CG ? &c.cs->n_active : nullptr;
   SliceOut<V> o{};
   o.x = static_cast<const V*>(c.x);
@@ -548,7 +610,7 @@ static nvd_status launch_sliced(const SpmmCall& c, const GridRed& red, hipStream
   o.b = c.b;
   o.ldb = c.ldb;
   o.cs = c.cs;
-  const int pass_grid = sg->S * sg->nch;   // S/8 rounds of 8 slices x nch chunks
+  const int pass_grid = sg->S * ((sg->nch + kSlGroup - 1) / kSlGroup);   // S/8 rounds x 8 slices x chunk groups
   const int comb_grid = std::min(sg->nch, kMaxBlocks);
   int pid = -1;
   if (prof_enabled()) {
@@ -559,17 +621,18 @@ static nvd_status launch_sliced(const SpmmCall& c, const GridRed& red, hipStream
     const double vecb = c.epi == EPI_RESID ? 3.0 * 8.0 * n : 2.0 * sv * n;
     pid = prof_begin(s, sizeof(V) == 8 ? PK_SPMM64 : PK_SPMM32, csr + vecb);
   }
+  constexpr bool DIFF = sizeof(V) == 8;
   if (unit)
-    k_slice_pass<V, true><<<pass_grid, kBS, 0, s>>>(a, o.x, o.ldx);
+    k_slice_pass<V, true, DIFF><<<pass_grid, kBS, 0, s>>>(a, o.x, o.ldx);
   else
-    k_slice_pass<V, false><<<pass_grid, kBS, 0, s>>>(a, o.x, o.ldx);
+    k_slice_pass<V, false, DIFF><<<pass_grid, kBS, 0, s>>>(a, o.x, o.ldx);
   bool ok = true;
   switch (c.epi) {
-    case EPI_PLAIN: k_slice_combine<V, EPI_PLAIN><<<comb_grid, kBS, 0, s>>>(a, o, red); break;
-    case EPI_CG: k_slice_combine<V, EPI_CG><<<comb_grid, kBS, 0, s>>>(a, o, red); break;
+    case EPI_PLAIN: k_slice_combine<V, EPI_PLAIN, DIFF><<<comb_grid, kBS, 0, s>>>(a, o, red); break;
+    case EPI_CG: k_slice_combine<V, EPI_CG, DIFF><<<comb_grid, kBS, 0, s>>>(a, o, red); break;
     case EPI_RESID:
       if constexpr (sizeof(V) == 8)
-        k_slice_combine<V, EPI_RESID><<<comb_grid, kBS, 0, s>>>(a, o, red);
+        k_slice_combine<V, EPI_RESID, DIFF><<<comb_grid, kBS, 0, s>>>(a, o, red);
       else
         ok = false;
       break;
