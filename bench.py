@@ -276,7 +276,8 @@ def bench_spmv(calib_copy=False, g=None):
         del X, Y
     dg.close()
     res = {"workload": "config_model_n1e7_unit_laplacian_apply", "n": g.n, "nnz": g.nnz,
-           "launches": rows, "traffic_k1_f32": load_spmv_traffic()}
+           "launches": rows, "traffic_k1_f32": load_spmv_traffic(),
+           "traffic_k1_f32_sliced": load_slice_traffic()}
     log("spmv: " + json.dumps(res))
     return res
 
@@ -310,6 +311,31 @@ def bench_single_pair(dg, P, Q, rtol, golden, reps=3):
                      "iters": info[0]["iters"], "rel_err_vs_oracle": err}
     log("single pair: " + json.dumps(res))
     return res
+
+
+SLICE_SOURCES = ("paper_2310_11222_amd/csrc/slice.hip", "paper_2310_11222_amd/csrc/device_common.hpp",
+                 "paper_2310_11222_amd/csrc/device_types.hpp")
+
+
+def slice_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for src in SLICE_SOURCES:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return h.hexdigest()
+
+
+def load_slice_traffic():
+    """Counter bytes per k = 1 FP32 apply by column slices (slice pass plus
+    combine) on the 10^7-node graph, from the committed profile, if taken on
+    the current source."""
+    p = os.path.join(ROOT, "profiles", "k_slice_f32_configmodel1e7_k1_traffic.md")
+    if not os.path.exists(p):
+        return None
+    fields = _profile_fields(p)
+    if fields.get("kernel_source_sha256") != slice_source_sha():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def load_spmv_traffic():

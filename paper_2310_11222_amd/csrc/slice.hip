@@ -8,7 +8,7 @@
 // lines of x do not stay in an XCD's 4 MB L2.  Here the columns (nodes) are
 // cut into S = 8m slices of at most kSlNodes nodes, so that one slice of x
 // fits in one XCD's L2, and the rows into chunks of kSlRows rows:
-//  * slice pass: block b works on slice s = 8r + (b mod 8) of kSlGroup
+//  * slice pass: block b works on slice s = 8r + (b mod 8) of a group of
 //    consecutive chunks, with the blocks of round r first.  The hardware
 //    deals consecutive blocks to the 8 XCDs round-robin, so every gather of a
 //    block hits the slice its XCD holds.  For every row of a chunk with
@@ -46,7 +46,9 @@ namespace nvd {
 
 constexpr int kSlRows = 2048;        // rows per chunk (LDS accumulator)
 constexpr int kSlLongItem = 32;      // neighbours above which an item takes a wave
-constexpr int kSlGroup = 8;          // chunks of one slice per block of the slice pass
+// Chunks of one slice per block of the slice pass: 8 for the FP32 pass; the
+// FP64 pass (which also reads each row's own x) measured faster with one.
+constexpr int slice_group(bool diff) { return diff ? 1 : 8; }
 constexpr int kSlNodes = 327680;     // nodes per slice: 2.5 MB of FP64 x
 constexpr int kSlMinN = 1 << 22;     // graphs this large use the slices by default
 
@@ -113,18 +115,19 @@ template <typename V, bool UNIT, bool DIFF>
 __global__ __launch_bounds__(kBS) void k_slice_pass(SliceArgs a, const V* __restrict__ x, long ldx) {
   using A = typename std::conditional<DIFF, V, double>::type;
   __shared__ int wsum[kBS / 64];
-  __shared__ long bnd[kSlGroup + 1];
-  __shared__ long bndl[kSlGroup + 1];
+  constexpr int G = slice_group(DIFF);
+  __shared__ long bnd[G + 1];
+  __shared__ long bndl[G + 1];
   if (a.gate && *a.gate == 0) return;
   // block -> (slice s, chunks c0 .. c0+cn-1); consecutive blocks go to the
   // 8 XCDs in turn, and the blocks of one round cover slices 8r .. 8r+7
-  const int ngrp = (a.nch + kSlGroup - 1) / kSlGroup;
+  const int ngrp = (a.nch + G - 1) / G;
   const int per_round = 8 * ngrp;
   const int r = (int)blockIdx.x / per_round;
   const int idx = (int)blockIdx.x - r * per_round;
   const int s = r * 8 + (idx & 7);
-  const int c0 = (idx >> 3) * kSlGroup;
-  const int cn = min(kSlGroup, a.nch - c0);
+  const int c0 = (idx >> 3) * G;
+  const int cn = min(G, a.nch - c0);
   const long k = (long)s * a.nch + c0;
   // the items (and neighbours) of consecutive chunks of one slice are
   // contiguous: the block walks them as one range
@@ -397,7 +400,10 @@ static nvd_status build_slices(DevGraph* g) {
     if (v >= 1) sn = v;
   }
   if (sn > n) sn = n;
+  // a multiple of 8 slices, all of about the same width (every XCD has work
+  // in every round)
   const int S = (int)(((n + sn - 1) / sn + 7) / 8 * 8);
+  sn = (n + S - 1) / S;
   const int nch = (int)((n + kSlRows - 1) / kSlRows);
   const long K = (long)S * nch;
   if (K > (1L << 31) / 8 || (long)8 * nch > (1L << 30)) {
@@ -610,7 +616,9 @@ static nvd_status launch_sliced(const SpmmCall& c, const GridRed& red, hipStream
   o.b = c.b;
   o.ldb = c.ldb;
   o.cs = c.cs;
-  const int pass_grid = sg->S * ((sg->nch + kSlGroup - 1) / kSlGroup);   // S/8 rounds x 8 slices x chunk groups
+  constexpr bool DIFF = sizeof(V) == 8;
+  constexpr int G = slice_group(DIFF);
+  const int pass_grid = sg->S * ((sg->nch + G - 1) / G);   // S/8 rounds x 8 slices x chunk groups
   const int comb_grid = std::min(sg->nch, kMaxBlocks);
   int pid = -1;
   if (prof_enabled()) {
@@ -621,7 +629,6 @@ static nvd_status launch_sliced(const SpmmCall& c, const GridRed& red, hipStream
     const double vecb = c.epi == EPI_RESID ? 3.0 * 8.0 * n : 2.0 * sv * n;
     pid = prof_begin(s, sizeof(V) == 8 ? PK_SPMM64 : PK_SPMM32, csr + vecb);
   }
-  constexpr bool DIFF = sizeof(V) == 8;
   if (unit)
     k_slice_pass<V, true, DIFF><<<pass_grid, kBS, 0, s>>>(a, o.x, o.ldx);
   else
