@@ -218,15 +218,18 @@ nvd_status nvd_graph_query(const nvd_graph* g, int32_t* labels_host,
  * graph's FP32 weight copy).  X and Y must not overlap.  Asynchronous:
  * returns once enqueued.
  * One column (k = 1, here and in the solvers' tiles of one pair) on a graph
- * of at least 2^22 nodes is applied by column slices: the nodes are cut into
- * slices whose part of X fits one XCD's L2, each XCD gathers from its own
- * slice, and per-row partial sums are added slice by slice in a fixed order.
- * The slice structure is built on the host at the first such call (that call
- * waits for the device once and then enqueues), kept with the graph (device
+ * of at least 2^20 nodes may be applied by column slices: the nodes are cut
+ * into slices whose part of X fits one XCD's L2, each XCD gathers from its
+ * own slice, and per-row partial sums are added slice by slice in a fixed
+ * order.  The first such call of each precision builds the slice structure
+ * on the host, times both forms of the apply on its X and keeps the faster
+ * for the graph (that call waits for the device and then enqueues).  The
+ * structure is kept with the graph while one precision uses it (device
  * memory: about 4 bytes per CSR entry, 12 more when weighted, plus 11 bytes
  * per row and slice with neighbours there) and dropped by
- * nvd_graph_set_weights and nvd_graph_destroy.  Environment: NVD_SLICE=0
- * never uses it, NVD_SLICE=1 uses it at any size. */
+ * nvd_graph_set_weights and nvd_graph_destroy.  nvd_distances_noalloc never
+ * uses it.  Environment: NVD_SLICE=0 never uses it, NVD_SLICE=1 uses it at
+ * any size without timing. */
 nvd_status nvd_laplacian_apply(nvd_graph* g, int32_t dtype, int32_t k,
                                const void* X, int64_t ldx, void* Y,
                                int64_t ldy, void* stream);

@@ -114,6 +114,7 @@ struct DevGraph {
   std::vector<int> heavy_deg_desc;  // host: their degrees
   SliceGraph* slices = nullptr; // built when the sliced apply is first needed
   int slice_state = 0;          // -1: build failed, use the row-wise apply
+  int slice_pick[2] = {0, 0};   // [FP64, FP32]: 1 sliced, -1 row-wise (timed), 0 not yet
 };
 
 struct Workspace {

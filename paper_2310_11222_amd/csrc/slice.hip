@@ -50,7 +50,7 @@ constexpr int kSlLongItem = 32;      // neighbours above which an item takes a w
 // FP64 pass (which also reads each row's own x) measured faster with one.
 constexpr int slice_group(bool diff) { return diff ? 1 : 8; }
 constexpr int kSlNodes = 327680;     // nodes per slice: 2.5 MB of FP64 x
-constexpr int kSlMinN = 1 << 22;     // graphs this large use the slices by default
+constexpr int kSlMinN = 1 << 20;     // graphs this large try the slices by default
 
 struct SliceGraph {
   int S = 0, nch = 0, sn = 0;
@@ -400,17 +400,36 @@ static nvd_status build_slices(DevGraph* g) {
     if (v >= 1) sn = v;
   }
   if (sn > n) sn = n;
-  // a multiple of 8 slices, all of about the same width (every XCD has work
-  // in every round)
-  const int S = (int)(((n + sn - 1) / sn + 7) / 8 * 8);
-  sn = (n + S - 1) / S;
+  const std::vector<int>& rp = g->h_rp;
+  // Slice boundaries: consecutive node ranges with about the same number of
+  // CSR entries (column j holds deg(j) of them: the graph is symmetric), so
+  // that the 8 XCDs of a round get about the same work even where degree
+  // follows the node id (preferential attachment puts the hubs first), and
+  // at most sn nodes each (one slice of x in an XCD's L2).  A multiple of 8.
+  const int S0 = (int)(((n + sn - 1) / sn + 7) / 8 * 8);
+  std::vector<int> slice_of(n);
+  int S = 0;
+  {
+    const double per = (double)g->nnz / S0;
+    long first = 0;
+    double acc = 0.0;
+    for (long j = 0; j < n; ++j) {
+      const double dj = (double)(rp[j + 1] - rp[j]);
+      if (j > first && (j - first >= sn || acc + 0.5 * dj > per * (S + 1))) {
+        ++S;
+        first = j;
+      }
+      slice_of[j] = S;
+      acc += dj;
+    }
+    S = (S + 1 + 7) / 8 * 8;
+  }
   const int nch = (int)((n + kSlRows - 1) / kSlRows);
   const long K = (long)S * nch;
   if (K > (1L << 31) / 8 || (long)8 * nch > (1L << 30)) {
     set_error("slices: graph too large for the sliced apply");
     return NVD_E_UNSUPPORTED;
   }
-  const std::vector<int>& rp = g->h_rp;
   const std::vector<int>& ci = g->h_ci;
   const bool wtd = g->weighted;
   const std::vector<double>& hw = g->h_w;
@@ -424,10 +443,10 @@ static nvd_status build_slices(DevGraph* g) {
     const long end = rp[i + 1];
     int prev = -1;
     while (e < end) {
-      const int s = (int)(ci[e] / sn);
+      const int s = slice_of[ci[e]];
       if (s < prev) return false;
       long f2 = e + 1;
-      while (f2 < end && ci[f2] / sn == s) ++f2;
+      while (f2 < end && slice_of[ci[f2]] == s) ++f2;
       f(s, e, (int)(f2 - e));
       prev = s;
       e = f2;
@@ -559,25 +578,6 @@ static nvd_status build_slices(DevGraph* g) {
   return NVD_OK;
 }
 
-// The sliced apply serves T = 1 once the graph has its slices; the first
-// eligible call builds them (state -1 after a failed build: the graph keeps
-// the row-wise apply).
-static bool use_slices(DevGraph* g, const SpmmCall& c) {
-  if (c.T != 1 || g->n < 1) return false;
-  const int mode = slice_mode();
-  if (mode == 0) return false;
-  if (mode == 2 && g->n < kSlMinN) return false;
-  if (g->slice_state < 0) return false;
-  if (!g->slices) {
-    if (build_slices(g) != NVD_OK) {
-      g->slice_state = -1;
-      return false;
-    }
-    g->slice_state = 1;
-  }
-  return true;
-}
-
 template <typename V>
 static nvd_status launch_sliced(const SpmmCall& c, const GridRed& red, hipStream_t s) {
   const DevGraph* g = c.g;
@@ -654,10 +654,79 @@ static nvd_status launch_sliced(const SpmmCall& c, const GridRed& red, hipStream
   return NVD_OK;
 }
 
+// Time the row-wise and the sliced apply of this call's x (EPI_PLAIN into a
+// scratch y, 3 launches each after a warm-up) and keep the faster per
+// precision.
+template <typename V>
+static nvd_status time_forms(DevGraph* g, const SpmmCall& c, const GridRed& red, hipStream_t s, float* t_row,
+                             float* t_sliced) {
+  void* y = nullptr;
+  NVD_HIP(hipMalloc(&y, sizeof(V) * (size_t)g->n));
+  SpmmCall t = c;
+  t.epi = EPI_PLAIN;
+  t.y = y;
+  t.ldy = 1;
+  t.b = nullptr;
+  t.cs = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  nvd_status st = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess ? NVD_OK : NVD_E_DEVICE;
+  for (int form = 0; form < 2 && st == NVD_OK; ++form) {
+    auto run = [&]() { return form == 0 ? launch_spmm(t, red, s) : launch_sliced<V>(t, red, s); };
+    st = run();
+    if (st == NVD_OK) st = hipEventRecord(a, s) == hipSuccess ? NVD_OK : NVD_E_DEVICE;
+    for (int i = 0; i < 3 && st == NVD_OK; ++i) st = run();
+    if (st == NVD_OK) st = hipEventRecord(b, s) == hipSuccess ? NVD_OK : NVD_E_DEVICE;
+    if (st == NVD_OK) st = hipEventSynchronize(b) == hipSuccess ? NVD_OK : NVD_E_DEVICE;
+    float ms = 0.0f;
+    if (st == NVD_OK) st = hipEventElapsedTime(&ms, a, b) == hipSuccess ? NVD_OK : NVD_E_DEVICE;
+    (form == 0 ? *t_row : *t_sliced) = ms;
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(y);
+  return st;
+}
+
+// The sliced apply serves T = 1 on graphs of at least kSlMinN nodes where it
+// is the faster form: the first eligible call of each precision builds the
+// slices (state -1 after a failed build: the graph keeps the row-wise apply)
+// and times both forms.  Calls with a bounded SpMM grid keep the row-wise
+// apply.
+static bool use_slices(DevGraph* g, const SpmmCall& c, const GridRed& red, hipStream_t s) {
+  // a caller that bounds the grid (the no-allocation entry point) has sized
+  // its reduction scratch for it, and building the slices would allocate
+  if (c.T != 1 || g->n < 1 || c.grid > 0) return false;
+  const int mode = slice_mode();
+  if (mode == 0) return false;
+  if (mode == 2 && g->n < kSlMinN) return false;
+  if (g->slice_state < 0) return false;
+  const int p = c.prec == 0 ? 0 : 1;
+  if (mode == 2 && g->slice_pick[p] < 0) return false;
+  if (!g->slices) {
+    if (build_slices(g) != NVD_OK) {
+      g->slice_state = -1;
+      return false;
+    }
+    g->slice_state = 1;
+  }
+  if (mode == 2 && g->slice_pick[p] == 0) {
+    float tr = 0.0f, ts = 0.0f;
+    const nvd_status st = c.prec == 0 ? time_forms<double>(g, c, red, s, &tr, &ts)
+                                      : time_forms<float>(g, c, red, s, &tr, &ts);
+    g->slice_pick[p] = (st == NVD_OK && ts < tr) ? 1 : -1;
+    if (g->slice_pick[0] < 0 && g->slice_pick[1] < 0) {
+      free_slices(g);
+      return false;
+    }
+  }
+  return mode == 1 || g->slice_pick[p] > 0;
+}
+
 nvd_status launch_apply(const SpmmCall& c, const GridRed& red, hipStream_t s) {
   if (c.g->n == 0) return NVD_OK;
   DevGraph* g = const_cast<DevGraph*>(c.g);
-  if (use_slices(g, c)) return c.prec == 0 ? launch_sliced<double>(c, red, s) : launch_sliced<float>(c, red, s);
+  if (use_slices(g, c, red, s)) return c.prec == 0 ? launch_sliced<double>(c, red, s) : launch_sliced<float>(c, red, s);
   return launch_spmm(c, red, s);
 }
 

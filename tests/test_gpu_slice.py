@@ -1,5 +1,5 @@
 """GPU parity of the one-column apply by XCD-pinned column slices.  Graphs of
-2^22 nodes and more use it by default; here it is forced on small graphs
+2^20 nodes and more use it where it times faster; here it is forced on small graphs
 with small slices (NVD_SLICE=1, NVD_SLICE_NODES), so that every case spans
 several slices and row chunks with a ragged last chunk, short items and
 hub rows with long items, and compared with the CPU oracle:
@@ -8,7 +8,9 @@ hub rows with long items, and compared with the CPU oracle:
   * bit-for-bit repeats and agreement with the row-wise apply;
   * distances solved one column at a time, both precisions, against the
     oracle's PCG and grounded routes;
-  * new weights after the slices were built.
+  * new weights after the slices were built;
+  * the timed choice on graphs of 2^20 nodes (BA and power-law), against the
+    row-wise apply.
 The single-launch solve is switched off (NVD_SMALL=0) so that the solves go
 through the sliced apply.  The 10^7-node case runs in test_gpu_full_size."""
 import numpy as np
@@ -151,3 +153,37 @@ def test_sliced_apply_after_new_weights(sliced):
     g2 = g.with_weights(w2)
     dg.set_weights(g2.w)
     _check_apply(dg, g2, X)
+
+
+@pytest.mark.parametrize("kind", ["ba", "powerlaw"])
+def test_auto_choice_at_1e6_nodes(monkeypatch, kind):
+    """Default mode on graphs of 2^20 nodes and more: the first one-column
+    call of each precision times both applies and keeps the faster.  Either
+    choice must give the distances of the row-wise apply (NVD_SLICE=0) and an
+    apply within the per-row bound, on sampled rows, of the definition."""
+    import torch
+    monkeypatch.delenv("NVD_SLICE", raising=False)
+    monkeypatch.setenv("NVD_SMALL", "0")
+    rng = np.random.default_rng(17)
+    n = (1 << 20) + 1000
+    if kind == "ba":
+        g = barabasi_albert(n, 3, rng)
+    else:
+        g = giant_component(configuration_model_powerlaw(n, 2.5, 3, int(n ** (1 / 1.5)), rng))
+    say("auto choice", kind, g.n, g.nnz)
+    dg = dev_graph(g)
+    P = np.where(rng.random((g.n, 1)) < 0.01, rng.random((g.n, 1)), 0.0)
+    Q = np.where(rng.random((g.n, 1)) < 0.01, rng.random((g.n, 1)), 0.0)
+    d_auto, _, info = dg.distances(P, Q, precision="mixed", rtol=1e-8, tile_k=1)
+    assert info[0]["status"] == 0
+    x = rng.standard_normal(g.n)
+    y32 = dg.laplacian_apply(torch.as_tensor(x).float().cuda()).cpu().numpy().ravel()
+    monkeypatch.setenv("NVD_SLICE", "0")
+    d_row, _, _ = dg.distances(P, Q, precision="mixed", rtol=1e-8, tile_k=1)
+    assert rel_err(d_auto.cpu().numpy(), d_row.cpu().numpy()).max() <= 1e-6
+    x32 = x.astype(np.float32).astype(np.float64)
+    for i in np.concatenate([rng.choice(g.n, 2000, replace=False), np.argsort(np.diff(g.row_ptr))[-10:]]):
+        nb = g.col_idx[g.row_ptr[i]:g.row_ptr[i + 1]]
+        want = np.sum(x32[i] - x32[nb])
+        scale = np.sum(np.abs(x32[i]) + np.abs(x32[nb]))
+        assert abs(y32[i] - want) <= 2e-6 * scale, i
