@@ -51,3 +51,16 @@ def test_reference_spmv_traffic_profile():
     if t is None:
         pytest.skip("profile predates the current kernel source")
     assert 4e8 < t < 2e10
+
+
+def test_sliced_apply_traffic_profile():
+    """The committed counters of the column-sliced one-column apply belong to
+    the current source and lie between the algorithmic bytes and the
+    row-wise apply's traffic."""
+    import bench
+    t = bench.load_slice_traffic()
+    assert t is not None, "profile predates the current slice.hip"
+    n, nnz = 10_000_000, 75_714_946
+    alg = 4.0 * nnz + 4.0 * (n + 1) + 2.0 * 4.0 * n
+    row = bench.load_spmv_traffic()
+    assert alg < t < (row if row is not None else 20 * alg)
