@@ -516,6 +516,30 @@ struct SVec {
   using type = typename VecOf<V, NE>::type;
 };
 
+// Loads and stores of the streaming passes (update, direction):
+// non-temporal.  Each vector is touched once per pass, and an XCD's share
+// of the batch's vectors (tens of MB) does not stay in its 4 MB L2 from one
+// pass to the next.  NVD_SWEEP_NT=0 builds plain accesses.
+#ifndef NVD_SWEEP_NT
+#define NVD_SWEEP_NT 1
+#endif
+template <typename VT>
+__device__ __forceinline__ VT sw_ld(const VT* p) {
+#if NVD_SWEEP_NT
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+template <typename VT>
+__device__ __forceinline__ void sw_st(const VT& v, VT* p) {
+#if NVD_SWEEP_NT
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
 // Inner set-up of an outer step for the open graphs: r = src - mean on open
 // columns (0 elsewhere), c = 0, p = D^-1 r; rho = r^T D^-1 r, ||r||^2.
 template <typename V, int T>
@@ -609,8 +633,8 @@ __global__ __launch_bounds__(SBS) void ks_update(SArgs a) {
     const long i1 = (long)hi * T / NE;
     for (long i = (long)lo * T / NE + t; i < i1; i += SBS) {
       V q[NE], r[NE];
-      unpack<V, NE>(Q4[i], q);
-      unpack<V, NE>(R4[i], r);
+      unpack<V, NE>(sw_ld(Q4 + i), q);
+      unpack<V, NE>(sw_ld(R4 + i), r);
 #pragma unroll
       for (int v = 0; v < NE; ++v) {
         r[v] -= al[v] * q[v];
@@ -618,7 +642,7 @@ __global__ __launch_bounds__(SBS) void ks_update(SArgs a) {
         acc[0][v] += rd * rd * (double)invd[(i * NE + v) / T];
         acc[1][v] += rd * rd;
       }
-      R4[i] = pack<V, NE>(r);
+      sw_st(pack<V, NE>(r), R4 + i);
     }
     chunk_block_sum<2, NE>(acc, T, sh, vals);
     if (chunk_arrive<2>(a, ch, g, sg.first, sg.nshort, vals, red)) {
@@ -684,20 +708,20 @@ __global__ __launch_bounds__(SBS) void ks_direction(SArgs a) {
     const long i1 = (long)hi * T / NE;
     for (long i = (long)lo * T / NE + t; i < i1; i += SBS) {
       V p[NE];
-      unpack<V, NE>(P4[i], p);
+      unpack<V, NE>(sw_ld(P4 + i), p);
       if (xup) {
         V cc[NE];
-        unpack<V, NE>(C4[i], cc);
+        unpack<V, NE>(sw_ld(C4 + i), cc);
 #pragma unroll
         for (int v = 0; v < NE; ++v) cc[v] += al[v] * p[v];
-        C4[i] = pack<V, NE>(cc);
+        sw_st(pack<V, NE>(cc), C4 + i);
       }
       if (pup) {
         V r[NE];
-        unpack<V, NE>(R4[i], r);
+        unpack<V, NE>(sw_ld(R4 + i), r);
 #pragma unroll
         for (int v = 0; v < NE; ++v) p[v] = r[v] * invd[(i * NE + v) / T] + be[v] * p[v];
-        P4[i] = pack<V, NE>(p);
+        sw_st(pack<V, NE>(p), P4 + i);
       }
     }
   }
