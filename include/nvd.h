@@ -225,8 +225,9 @@ nvd_status nvd_graph_query(const nvd_graph* g, int32_t* labels_host,
  * on the host, times both forms of the apply on its X and keeps the faster
  * for the graph (that call waits for the device and then enqueues).  The
  * structure is kept with the graph while one precision uses it (device
- * memory: about 4 bytes per CSR entry, 12 more when weighted, plus 11 bytes
- * per row and slice with neighbours there) and dropped by
+ * memory: about 4 bytes per CSR entry, plus 11 bytes per row and slice with
+ * neighbours there; weighted graphs 12 more per entry and 8 per row) and
+ * dropped by
  * nvd_graph_set_weights and nvd_graph_destroy.  nvd_distances_noalloc never
  * uses it.  Environment: NVD_SLICE=0 never uses it, NVD_SLICE=1 uses it at
  * any size without timing. */
