@@ -227,8 +227,7 @@ nvd_status nvd_graph_query(const nvd_graph* g, int32_t* labels_host,
  * structure is kept with the graph while one precision uses it (device
  * memory: about 4 bytes per CSR entry, plus 11 bytes per row and slice with
  * neighbours there; weighted graphs 12 more per entry and 8 per row) and
- * dropped by
- * nvd_graph_set_weights and nvd_graph_destroy.  nvd_distances_noalloc never
+ * dropped by nvd_graph_set_weights and nvd_graph_destroy.  nvd_distances_noalloc never
  * uses it.  Environment: NVD_SLICE=0 never uses it, NVD_SLICE=1 uses it at
  * any size without timing. */
 nvd_status nvd_laplacian_apply(nvd_graph* g, int32_t dtype, int32_t k,
