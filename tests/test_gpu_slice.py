@@ -10,7 +10,8 @@ hub rows with long items, and compared with the CPU oracle:
     oracle's PCG and grounded routes;
   * new weights after the slices were built;
   * the timed choice on graphs of 2^20 nodes (BA and power-law), against the
-    row-wise apply.
+    row-wise apply;
+  * tree- and approximate-Cholesky-preconditioned solves (smooth directions).
 The single-launch solve is switched off (NVD_SMALL=0) so that the solves go
 through the sliced apply.  The 10^7-node case runs in test_gpu_full_size."""
 import numpy as np
@@ -187,3 +188,41 @@ def test_auto_choice_at_1e6_nodes(monkeypatch, kind):
         want = np.sum(x32[i] - x32[nb])
         scale = np.sum(np.abs(x32[i]) + np.abs(x32[nb]))
         assert abs(y32[i] - want) <= 2e-6 * scale, i
+
+
+@pytest.mark.parametrize("precond", ["tree", "achol"])
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-10, 1e-8), ("mixed", 1e-8, 1e-6)])
+def test_sliced_apply_with_strong_preconditioners(sliced, precond, precision, rtol, tol):
+    """A preconditioner close to L^+ (the augmented forest, the approximate
+    Cholesky factor) makes the CG directions smooth, with a large spread on
+    a long near-tree: the case where a plain sum d x_v - sum w x_u would lose
+    FP32 digits.  The sliced FP32 apply sums the partials in FP64, so these
+    solves must reach the same accuracy as with the row-wise apply.  A
+    2,000-node random tree with 30 extra edges and lognormal weights, plus a
+    path of 3,000 nodes (its own component), one pair per tile."""
+    sliced(500)
+    rng = np.random.default_rng(23)
+    n1 = 2000
+    parent = np.array([rng.integers(0, i) for i in range(1, n1)])
+    eu = [np.arange(1, n1), rng.integers(0, n1, 30)]
+    ev = [parent, rng.integers(0, n1, 30)]
+    n2 = 3000
+    eu.append(np.arange(n1, n1 + n2 - 1))
+    ev.append(np.arange(n1 + 1, n1 + n2))
+    eu = np.concatenate(eu)
+    ev = np.concatenate(ev)
+    keep = eu != ev
+    eu, ev = eu[keep], ev[keep]
+    key = np.unique(np.minimum(eu, ev).astype(np.int64) * (n1 + n2) + np.maximum(eu, ev))
+    eu, ev = key // (n1 + n2), key % (n1 + n2)
+    g = Graph(n1 + n2, eu, ev, rng.lognormal(0.0, 1.0, eu.size))
+    P = np.where(rng.random((g.n, 2)) < 0.1, rng.random((g.n, 2)), 0.0)
+    Q = np.where(rng.random((g.n, 2)) < 0.1, rng.random((g.n, 2)), 0.0)
+    say("sliced with", precond, precision, g.n, g.nnz)
+    dg = dev_graph(g)
+    b0 = dg.stats()["device_bytes"]
+    d, _, info = dg.distances(P, Q, precision=precision, rtol=rtol, tile_k=1, precond=precond)
+    assert dg.stats()["device_bytes"] > b0
+    assert all(i["status"] == 0 for i in info), info
+    ref = oracle.ge_grounded(g.n, g.row_ptr, g.col_idx, g.w, P, Q)["d"]
+    assert rel_err(d.cpu().numpy(), ref).max() <= tol
