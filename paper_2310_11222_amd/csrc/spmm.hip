@@ -26,8 +26,9 @@
 //    counter), so results do not depend on timing.  (One wave per segment
 //    was measured slower: at T = 32 a wave has a quarter of a block's
 //    neighbour slots, and the longest hub segment sets the kernel's time.)
-// The CSR and the output are touched once per pass and are loaded and stored
-// non-temporally.
+// The output is stored non-temporally (touched once per pass).  The CSR is
+// read with ordinary loads: non-temporal ones made each of a row's unrolled
+// index loads fetch the same lines again (NVD_NT_CSR=1 builds them).
 // Epilogues fuse the consumer of L X:
 //  * EPI_PLAIN: store Y.
 //  * EPI_CG:    q = L p, store q and reduce sigma_c = p_c^T q_c; the grid's
