@@ -11,7 +11,8 @@ hub rows with long items, and compared with the CPU oracle:
   * new weights after the slices were built;
   * the timed choice on graphs of 2^20 nodes (BA and power-law), against the
     row-wise apply;
-  * tree- and approximate-Cholesky-preconditioned solves (smooth directions).
+  * tree- and approximate-Cholesky-preconditioned solves (smooth directions);
+  * a warm start from the oracle's x, the squared output and the returned x.
 The single-launch solve is switched off (NVD_SMALL=0) so that the solves go
 through the sliced apply.  The 10^7-node case runs in test_gpu_full_size."""
 import numpy as np
@@ -226,3 +227,25 @@ def test_sliced_apply_with_strong_preconditioners(sliced, precond, precision, rt
     assert all(i["status"] == 0 for i in info), info
     ref = oracle.ge_grounded(g.n, g.row_ptr, g.col_idx, g.w, P, Q)["d"]
     assert rel_err(d.cpu().numpy(), ref).max() <= tol
+
+
+def test_sliced_warm_start_and_squared_output(sliced):
+    """Tiles of one column through the sliced apply: a warm start from the
+    oracle's solution converges at once to the oracle's distances, and the
+    squared output and the returned x match the oracle (FP64)."""
+    sliced(1200)
+    g = _powerlaw(29)
+    rng = np.random.default_rng(31)
+    g = g.with_weights(rng.uniform(0.5, 2.0, g.num_edges))
+    P = np.where(rng.random((g.n, 2)) < 0.1, rng.random((g.n, 2)), 0.0)
+    Q = np.where(rng.random((g.n, 2)) < 0.1, rng.random((g.n, 2)), 0.0)
+    # the PCG route (an LU of this expander's grounded Laplacian fills in)
+    ref = oracle.ge_pcg(g.n, g.row_ptr, g.col_idx, g.w, P, Q)
+    say("sliced warm start", g.n)
+    dg = dev_graph(g)
+    dsq, X, info = dg.distances(P, Q, precision="fp64", rtol=1e-10, tile_k=1, return_x=True, out="dsq")
+    assert rel_err(dsq.cpu().numpy(), ref["dsq"]).max() <= 1e-8
+    np.testing.assert_allclose(X.cpu().numpy(), ref["x"], rtol=0, atol=1e-7 * np.abs(ref["x"]).max())
+    d, _, info = dg.distances(P, Q, precision="fp64", rtol=1e-10, tile_k=1, X0=ref["x"])
+    assert rel_err(d.cpu().numpy(), ref["d"]).max() <= 1e-8
+    assert all(i["iters"] <= 2 for i in info), [i["iters"] for i in info]
